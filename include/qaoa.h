@@ -1,0 +1,202 @@
+/*
+ * qaoa.h -- C ABI of the MI355X (gfx950) QAOA max-cut state-vector simulator.
+ *
+ * The simulated circuit is the max-cut QAOA of Lin, Wang, Tu and Hung,
+ * "Towards Optimizations of Quantum Circuit Simulation for Solving Max-Cut
+ * Problems with QAOA" (arXiv:2312.03019):
+ *   - n qubits, a dense state vector of 2^n complex amplitudes indexed by z,
+ *     qubit q <-> bit q of z (the bit extraction (b >> i) & 1 of Algorithm 3);
+ *   - start |+>^n: every amplitude 2^(-n/2) ("launch control", Section
+ *     Mathematical Optimizations);
+ *   - p layers; layer l applies the diagonal cost unitary exp(-i gamma_l C(z))
+ *     (rotation compression, Eq. UC_opt / Algorithm 2), with the cut value
+ *     C(z) = sum over edges of w_uv [z_u != z_v] (bitwise popcount form of
+ *     Algorithm 3 for unweighted graphs), then the mixer exp(-i beta_l X_q) =
+ *     RX(2 beta_l) on every qubit (mixer layer of Algorithm 1);
+ *   - the objective <C> = sum_z |psi_z|^2 C(z).
+ * The paper prints its cost layer as exp(-i gamma/2 sum w Z_i Z_j) and its
+ * mixer as RX(beta); those equal this ABI's gamma -> -gamma, beta -> beta/2 up
+ * to a global phase.  The ABI fixes the convention above and takes no flag.
+ *
+ * Conventions for every call:
+ *   - Return value: QAOA_OK (0) or a negative QAOA_E* code; nothing throws or
+ *     aborts.  qaoa_last_error() gives a thread-local message for the last
+ *     failure on the calling thread.
+ *   - Ownership: the caller owns every input array; the library copies what
+ *     it keeps before returning.  Output arrays are caller-provided host
+ *     memory unless stated.  Device state is owned by the library unless the
+ *     caller lends a buffer with qaoa_bind_state.
+ *   - Threads: one context must not be used from two threads at once (the
+ *     second caller gets QAOA_ESTATE).  A server handle is thread-safe.
+ *   - Device errors (HIP) are reported as QAOA_EDEVICE with the HIP message.
+ */
+#ifndef QAOA_H
+#define QAOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  QAOA_OK = 0,
+  QAOA_EINVAL = -1,    /* invalid argument */
+  QAOA_ENOMEM = -2,    /* device or host memory, or serving budget, exhausted */
+  QAOA_EDEVICE = -3,   /* HIP runtime error */
+  QAOA_EPENDING = -4,  /* serving: result not ready yet */
+  QAOA_ECANCELED = -5, /* serving: request was cancelled */
+  QAOA_ESTATE = -6     /* call out of order, or context busy on another thread */
+};
+
+enum { QAOA_C128 = 0, QAOA_C64 = 1 }; /* state precision: complex double / complex float */
+
+typedef struct qaoa_ctx qaoa_ctx;
+typedef struct qaoa_server qaoa_server;
+
+/* Create a simulator for one max-cut instance (Table 1's N, graph and w).
+ * n: qubits = vertices, 1 <= n <= qaoa_max_qubits(prec, 0).
+ * edges: 2*num_edges int32 vertex ids u0,v0,u1,v1,... with 0 <= u,v < n,
+ *   u != v, each unordered pair at most once (the paper's upper-triangular
+ *   graph holds one weight per pair).  num_edges = 0 is valid (C = 0).
+ * weights: num_edges finite doubles, or NULL for the unweighted graph (all
+ *   weights 1; cut values are then exact integers).
+ * prec: QAOA_C128 or QAOA_C64.  With QAOA_C64 the state is complex float;
+ *   phase angles gamma*C(z) are formed and reduced in double before the
+ *   single-precision sine/cosine, and all reductions run in double.
+ * The context binds to the current HIP device and allocates no state until
+ * the first run.  Validation happens before any device call. */
+int qaoa_create(int n, int num_edges, const int32_t *edges, const double *weights,
+                int prec, qaoa_ctx **out);
+
+/* Release everything the context owns (a bound state buffer is not freed). */
+void qaoa_destroy(qaoa_ctx *ctx);
+
+/* Largest n whose state (times two vectors when with_grad) fits the current
+ * device's free memory for the given precision; 0 when no device. */
+int qaoa_max_qubits(int prec, int with_grad);
+
+/* Evolve |+>^n through p layers (p >= 0) with angles gamma[p], beta[p]
+ * (finite doubles).  Enqueues work on the bound stream and returns; the
+ * state stays on the device.  p = 0 leaves |+>^n. */
+int qaoa_run(qaoa_ctx *ctx, int p, const double *gamma, const double *beta);
+
+/* <C> and the norm sum |psi|^2 of the last qaoa_run (both double; the norm
+ * pointer may be NULL).  Synchronises the stream.  QAOA_ESTATE before any run. */
+int qaoa_expect(qaoa_ctx *ctx, double *expect_out, double *norm_out);
+
+/* <C> and its gradient d<C>/dgamma_l, d<C>/dbeta_l for l < p, by one forward
+ * sweep and one adjoint backward sweep on the device (two state vectors).
+ * dgamma and dbeta are caller arrays of p doubles.  Leaves the final state
+ * psi_p on the device as qaoa_run would. */
+int qaoa_grad(qaoa_ctx *ctx, int p, const double *gamma, const double *beta,
+              double *expect_out, double *dgamma, double *dbeta);
+
+/* Cut value C(z) for all 2^n z (the per-state totals of Algorithms 2/3, in the
+ * max-cut form).  Unweighted: int32 values (bytes = 4*2^n), exact.
+ * Weighted: double values (bytes = 8*2^n).  host_out is host memory. */
+int qaoa_cut_table(qaoa_ctx *ctx, void *host_out, size_t bytes);
+
+/* Copy the state of the last run to host memory: 2^n interleaved
+ * (re, im) pairs of double (C128) or float (C64); bytes must match. */
+int qaoa_get_state(qaoa_ctx *ctx, void *host_out, size_t bytes);
+
+/* F = |<a|b>|^2 / (<a|a><b|b>) between the states of two contexts with the
+ * same n (precisions may differ), accumulated in double on the device. */
+int qaoa_fidelity(qaoa_ctx *a, qaoa_ctx *b, double *f_out);
+
+/* Launch all further work of this context on an existing HIP stream
+ * (hipStream_t passed as void*; NULL = the null stream).  The caller keeps
+ * the stream alive while the context uses it. */
+int qaoa_bind_stream(qaoa_ctx *ctx, void *hip_stream);
+
+/* Use caller-owned device memory (e.g. a torch tensor) as the state vector.
+ * bytes must be exactly 2^n * (16 for C128, 8 for C64); dev_ptr must be
+ * 256-byte aligned device memory that outlives the context's use of it. */
+int qaoa_bind_state(qaoa_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Per-pass kernel timing of later runs: when enabled, every pass launch is
+ * bracketed by HIP events on the bound stream. */
+int qaoa_set_profiling(qaoa_ctx *ctx, int enable);
+
+/* Kernel times (ms) of the passes of the last run, in launch order, plus each
+ * pass's algorithmic HBM bytes (state bytes read + written).  Fills at most
+ * max entries of ms[] and bytes[] (either may be NULL) and returns the pass
+ * count through *count.  Synchronises the stream. */
+int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count);
+
+/* Plan of a run of depth p: number of HBM passes, number of qubit sets the
+ * mixer is split into, and the qubits per set (sizes[] up to max_sets). */
+int qaoa_plan_info(qaoa_ctx *ctx, int p, int *passes, int *sets, int *sizes, int max_sets);
+
+/* Bandwidth reference: copy bytes (a multiple of 16) from src to dst, both
+ * device pointers, with a plain streaming kernel on the given stream. */
+int qaoa_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
+
+/* Thread-local message describing the last failure on this thread. */
+const char *qaoa_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of <C> and gradient requests.
+ * A scheduler thread admits queued requests while the sum of their device
+ * footprints stays within hbm_budget_bytes and fewer than max_slots are
+ * active, then advances every active request by one HBM pass per step, all
+ * of a step's passes in one batched kernel launch.  Requests that arrive
+ * while others run join at the next step; finished ones retire and free
+ * their memory at once.  Each request's arithmetic (tiles, per-tile partial
+ * slots, reduction order) is independent of what it shares a step with, so
+ * its result is bitwise the same alone or in a mix.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int n;                  /* 1 <= n <= 34 */
+  int num_edges;
+  const int32_t *edges;   /* as in qaoa_create */
+  const double *weights;  /* NULL = unweighted */
+  int p;                  /* >= 0 */
+  const double *gamma;    /* p values */
+  const double *beta;     /* p values */
+  int want_grad;          /* also return d<C>/dgamma, d<C>/dbeta */
+} qaoa_request;
+
+typedef struct {
+  int status;             /* QAOA_OK or an error code */
+  double expect, norm;
+  double *dgamma, *dbeta; /* caller arrays of p doubles, filled when want_grad */
+  double t_arrival, t_admit, t_done;  /* seconds on the server's clock */
+} qaoa_result;
+
+/* Start a server on the current device.  prec: QAOA_C64 or QAOA_C128. */
+int qaoa_serve_create(size_t hbm_budget_bytes, int max_slots, int prec, qaoa_server **out);
+
+/* Queue a request (inputs are copied).  A request whose footprint exceeds the
+ * whole budget is refused with QAOA_ENOMEM.  *ticket identifies it.
+ * arrival_time < 0 stamps the submit time; otherwise it is taken as the
+ * arrival instant (server clock) for latency accounting. */
+int qaoa_serve_submit(qaoa_server *srv, const qaoa_request *req, double arrival_time,
+                      uint64_t *ticket);
+
+/* Non-blocking: QAOA_OK with *out filled, QAOA_EPENDING, or the request's
+ * error.  A collected result is forgotten by the server. */
+int qaoa_serve_poll(qaoa_server *srv, uint64_t ticket, qaoa_result *out);
+
+/* Blocking form of poll with a timeout in seconds (< 0 waits forever). */
+int qaoa_serve_wait(qaoa_server *srv, uint64_t ticket, qaoa_result *out, double timeout_s);
+
+/* Cancel a queued or running request; its result becomes QAOA_ECANCELED. */
+int qaoa_serve_cancel(qaoa_server *srv, uint64_t ticket);
+
+/* Throughput and latency (arrival -> done) over completed requests. */
+int qaoa_serve_stats(qaoa_server *srv, double *req_per_s, double *p50_s, double *p99_s);
+
+/* Seconds on the server's clock (the time base of t_arrival and friends). */
+double qaoa_serve_clock(qaoa_server *srv);
+
+/* Stop the scheduler; queued and running requests are cancelled. */
+int qaoa_serve_destroy(qaoa_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAOA_H */

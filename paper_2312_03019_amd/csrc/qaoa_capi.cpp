@@ -1,0 +1,487 @@
+// C ABI: simulator contexts (qaoa_create ... qaoa_destroy).
+#include <math.h>
+#include <string.h>
+
+#include <atomic>
+#include <vector>
+
+#include "../../include/qaoa.h"
+#include "qaoa_runtime.h"
+
+namespace qaoa {
+const char* last_error();
+}
+
+using namespace qaoa;
+
+#define HIPCHK(expr)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      set_error("%s failed: %s", #expr, hipGetErrorString(e_));               \
+      return e_ == hipErrorOutOfMemory ? QAOA_ENOMEM : QAOA_EDEVICE;          \
+    }                                                                         \
+  } while (0)
+
+struct qaoa_ctx {
+  HostGraph hg;
+  int prec = QAOA_C128;
+  int device = 0;
+  bool dev_ready = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool stream_bound = false;
+  void* psi = nullptr;
+  bool own_psi = false;
+  size_t state_bytes = 0;
+  void* lam = nullptr;
+  void* dgraph = nullptr;
+  char* dev_img = nullptr;
+  size_t dev_img_cap = 0;
+  double* dev_part = nullptr;
+  size_t dev_part_cap = 0;
+  double* dev_out = nullptr;
+  size_t dev_out_cap = 0;
+  char* host_img = nullptr;
+  size_t host_img_cap = 0;
+  double* host_out = nullptr;
+  size_t host_out_cap = 0;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  bool have_state = false;
+  bool have_expect = false;
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  int ntimed = 0;
+  std::vector<double> pass_bytes;
+  std::atomic<int> busy{0};
+};
+
+namespace {
+
+struct Busy {
+  qaoa_ctx* c;
+  bool ok;
+  explicit Busy(qaoa_ctx* ctx) : c(ctx), ok(ctx && ctx->busy.exchange(1) == 0) {}
+  ~Busy() {
+    if (ok) c->busy.store(0);
+  }
+};
+
+int grow_device(void** p, size_t* cap, size_t need, hipStream_t st) {
+  if (*cap >= need && *p) return QAOA_OK;
+  if (*p) {
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+  }
+  size_t sz = need < 4096 ? 4096 : need + need / 2;
+  HIPCHK(hipMalloc(p, sz));
+  *cap = sz;
+  return QAOA_OK;
+}
+
+int grow_host(void** p, size_t* cap, size_t need, qaoa_ctx* c) {
+  if (*cap >= need && *p) return QAOA_OK;
+  if (*p) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipHostFree(*p));
+    *p = nullptr;
+    *cap = 0;
+  }
+  size_t sz = need < 4096 ? 4096 : need + need / 2;
+  HIPCHK(hipHostMalloc(p, sz, hipHostMallocDefault));
+  *cap = sz;
+  return QAOA_OK;
+}
+
+int ensure_device(qaoa_ctx* c) {
+  if (c->dev_ready) return QAOA_OK;
+  HIPCHK(hipGetDevice(&c->device));
+  if (!c->stream && !c->stream_bound) {
+    // default: a private non-blocking stream at default priority
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  const size_t gb = dev_graph_bytes(c->hg);
+  HIPCHK(hipMalloc(&c->dgraph, gb));
+  std::vector<char> img(gb);
+  build_dev_graph_image(c->hg, img.data(), c->dgraph);
+  HIPCHK(hipMemcpy(c->dgraph, img.data(), gb, hipMemcpyHostToDevice));
+  if (!c->psi) {
+    HIPCHK(hipMalloc(&c->psi, c->state_bytes));
+    c->own_psi = true;
+  }
+  HIPCHK(hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming));
+  c->dev_ready = true;
+  return QAOA_OK;
+}
+
+int check_angles(int p, const double* g, const double* b) {
+  if (p < 0 || p > 100000 || (p > 0 && (!g || !b))) {
+    set_error("invalid p or angle arrays");
+    return QAOA_EINVAL;
+  }
+  for (int l = 0; l < p; ++l)
+    if (!std::isfinite(g[l]) || !std::isfinite(b[l])) {
+      set_error("angle %d is not finite", l);
+      return QAOA_EINVAL;
+    }
+  return QAOA_OK;
+}
+
+// Build, upload and launch one run (forward, and the adjoint sweep if grad).
+int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool grad) {
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  if (grad && !c->lam) HIPCHK(hipMalloc(&c->lam, c->state_bytes));
+  RunRequest rq{&c->hg, c->prec, p, gamma, beta, grad, c->psi, c->lam, (const GraphDev*)c->dgraph};
+  RunImage img;
+  build_run(rq, &img);
+  const ImageLayout lay = image_layout(img, c->prec);
+  if (c->upload_pending) {
+    HIPCHK(hipEventSynchronize(c->upload_done));
+    c->upload_pending = false;
+  }
+  if ((rc = grow_device((void**)&c->dev_img, &c->dev_img_cap, lay.total, c->stream))) return rc;
+  if ((rc = grow_device((void**)&c->dev_part, &c->dev_part_cap, img.part_doubles * sizeof(double), c->stream)))
+    return rc;
+  if ((rc = grow_device((void**)&c->dev_out, &c->dev_out_cap, img.nout * sizeof(double), c->stream))) return rc;
+  if ((rc = grow_host((void**)&c->host_img, &c->host_img_cap, lay.total, c))) return rc;
+  if ((rc = grow_host((void**)&c->host_out, &c->host_out_cap, img.nout * sizeof(double), c))) return rc;
+  pack_run(img, lay, c->prec, c->host_img, c->dev_img, c->dev_part, c->dev_out);
+  HIPCHK(hipMemcpyAsync(c->dev_img, c->host_img, lay.total, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipEventRecord(c->upload_done, c->stream));
+  c->upload_pending = true;
+
+  const PrecCfg pc = prec_cfg(c->prec);
+  int K, logr;
+  tile_shape(c->hg.n, pc, &K, &logr);
+  const int nthreads = 1 << (K - logr);
+  const int64_t ntiles = (int64_t)1 << (c->hg.n - K);
+  const size_t nf = img.fwd.size();
+  if (c->profiling) {
+    while (c->ev.size() < 2 * nf) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      c->ev.push_back(e);
+    }
+  }
+  const PassDesc* dfwd = (const PassDesc*)(c->dev_img + lay.off_fwd);
+  for (size_t i = 0; i < nf; ++i) {
+    if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * i], c->stream));
+    HIPCHK(launch_pass(pc.prec, false, logr, dfwd + i, 1, ntiles, nthreads, c->stream));
+    if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * i + 1], c->stream));
+  }
+  c->ntimed = c->profiling ? (int)nf : 0;
+  c->pass_bytes = img.pass_bytes;
+  const PassDesc* dbwd = (const PassDesc*)(c->dev_img + lay.off_bwd);
+  for (size_t i = 0; i < img.bwd.size(); ++i)
+    HIPCHK(launch_pass(pc.prec, true, logr, dbwd + i, 1, ntiles, nthreads, c->stream));
+  HIPCHK(launch_reduce((const ReduceJob*)(c->dev_img + lay.off_jobs), (const Span*)(c->dev_img + lay.off_spans),
+                       (int)img.jobs.size(), c->stream));
+  HIPCHK(hipMemcpyAsync(c->host_out, c->dev_out, img.nout * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return QAOA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qaoa_last_error(void) { return qaoa::last_error(); }
+
+int qaoa_create(int n, int num_edges, const int32_t* edges, const double* weights, int prec, qaoa_ctx** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return QAOA_EINVAL;
+  }
+  *out = nullptr;
+  if (prec != QAOA_C128 && prec != QAOA_C64) {
+    set_error("prec must be QAOA_C128 or QAOA_C64");
+    return QAOA_EINVAL;
+  }
+  HostGraph hg;
+  int rc = make_graph(n, num_edges, edges, weights, &hg);
+  if (rc) return rc;
+  qaoa_ctx* c = new qaoa_ctx();
+  c->hg = std::move(hg);
+  c->prec = prec;
+  c->state_bytes = ((size_t)1 << n) * prec_cfg(prec).elem;
+  *out = c;
+  return QAOA_OK;
+}
+
+void qaoa_destroy(qaoa_ctx* c) {
+  if (!c) return;
+  if (c->dev_ready && c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->own_psi && c->psi) (void)hipFree(c->psi);
+  if (c->lam) (void)hipFree(c->lam);
+  if (c->dgraph) (void)hipFree(c->dgraph);
+  if (c->dev_img) (void)hipFree(c->dev_img);
+  if (c->dev_part) (void)hipFree(c->dev_part);
+  if (c->dev_out) (void)hipFree(c->dev_out);
+  if (c->host_img) (void)hipHostFree(c->host_img);
+  if (c->host_out) (void)hipHostFree(c->host_out);
+  if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int qaoa_max_qubits(int prec, int with_grad) {
+  if (prec != QAOA_C128 && prec != QAOA_C64) return 0;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 0;
+  const size_t elem = prec_cfg(prec).elem;
+  const size_t margin = (size_t)256 << 20;
+  int best = 0;
+  for (int n = 1; n <= kMaxN; ++n) {
+    const size_t need = ((size_t)1 << n) * elem * (with_grad ? 2 : 1) + margin;
+    if (need <= fr) best = n;
+  }
+  return best;
+}
+
+int qaoa_run(qaoa_ctx* c, int p, const double* gamma, const double* beta) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  int rc = check_angles(p, gamma, beta);
+  if (rc) return rc;
+  c->have_state = c->have_expect = false;
+  rc = launch_run(c, p, gamma, beta, false);
+  if (rc) return rc;
+  c->have_state = c->have_expect = true;
+  return QAOA_OK;
+}
+
+int qaoa_expect(qaoa_ctx* c, double* expect_out, double* norm_out) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  if (!c->have_expect) {
+    set_error("no run to take the expectation of");
+    return QAOA_ESTATE;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (expect_out) *expect_out = c->host_out[0];
+  if (norm_out) *norm_out = c->host_out[1];
+  return QAOA_OK;
+}
+
+int qaoa_grad(qaoa_ctx* c, int p, const double* gamma, const double* beta, double* expect_out, double* dgamma,
+              double* dbeta) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  int rc = check_angles(p, gamma, beta);
+  if (rc) return rc;
+  if (p > 0 && (!dgamma || !dbeta)) {
+    set_error("dgamma/dbeta are NULL");
+    return QAOA_EINVAL;
+  }
+  c->have_state = c->have_expect = false;
+  rc = launch_run(c, p, gamma, beta, true);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (expect_out) *expect_out = c->host_out[0];
+  for (int l = 0; l < p; ++l) {
+    dgamma[l] = c->host_out[2 + l];
+    dbeta[l] = c->host_out[2 + p + l];
+  }
+  c->have_expect = true;     // the state buffer now holds an intermediate of the adjoint sweep
+  return QAOA_OK;
+}
+
+int qaoa_cut_table(qaoa_ctx* c, void* host_out, size_t bytes) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  const size_t N = (size_t)1 << c->hg.n;
+  const size_t need = N * (c->hg.weighted() ? 8 : 4);
+  if (!host_out || bytes != need) {
+    set_error("cut table needs %zu bytes", need);
+    return QAOA_EINVAL;
+  }
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  void* d = nullptr;
+  HIPCHK(hipMalloc(&d, need));
+  hipError_t e = launch_cut_table((const GraphDev*)c->dgraph, c->hg.weighted(), d, (int64_t)N, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(host_out, d, need, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) {
+    set_error("cut table: %s", hipGetErrorString(e));
+    return QAOA_EDEVICE;
+  }
+  return QAOA_OK;
+}
+
+int qaoa_get_state(qaoa_ctx* c, void* host_out, size_t bytes) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  if (!c->have_state) {
+    set_error("no state: run first (a gradient run leaves no final state)");
+    return QAOA_ESTATE;
+  }
+  if (!host_out || bytes != c->state_bytes) {
+    set_error("state needs %zu bytes", c->state_bytes);
+    return QAOA_EINVAL;
+  }
+  HIPCHK(hipMemcpyAsync(host_out, c->psi, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return QAOA_OK;
+}
+
+int qaoa_fidelity(qaoa_ctx* a, qaoa_ctx* b, double* f_out) {
+  if (!a || !b || !f_out || a == b) {
+    set_error("invalid arguments");
+    return QAOA_EINVAL;
+  }
+  Busy ba(a), bb(b);
+  if (!ba.ok || !bb.ok) {
+    set_error("context busy");
+    return QAOA_ESTATE;
+  }
+  if (a->hg.n != b->hg.n) {
+    set_error("qubit counts differ");
+    return QAOA_EINVAL;
+  }
+  if (!a->have_state || !b->have_state) {
+    set_error("both contexts need a state");
+    return QAOA_ESTATE;
+  }
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int64_t N = (int64_t)1 << a->hg.n;
+  int nb = (int)std::min<int64_t>(2048, (N + 255) / 256);
+  // partials | jobs | spans | out
+  const size_t part_b = 4 * (size_t)nb * sizeof(double);
+  const size_t total = part_b + 4 * sizeof(ReduceJob) + 4 * sizeof(Span) + 4 * sizeof(double) + 256;
+  char* d = nullptr;
+  HIPCHK(hipMalloc(&d, total));
+  char* dj = d + part_b;
+  char* ds = dj + 4 * sizeof(ReduceJob);
+  double* dout = (double*)(ds + 4 * sizeof(Span));
+  ReduceJob jobs[4];
+  Span spans[4];
+  for (int k = 0; k < 4; ++k) {
+    memset(&jobs[k], 0, sizeof jobs[k]);
+    jobs[k].span_begin = k;
+    jobs[k].span_end = k + 1;
+    jobs[k].out = dout + k;
+    jobs[k].scale = 1.0;
+    spans[k] = Span{(const double*)d + (int64_t)k * nb, nb};
+  }
+  double h[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpy(dj, jobs, sizeof jobs, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ds, spans, sizeof spans, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_overlap(a->prec, a->psi, b->prec, b->psi, N, (double*)d, nb, a->stream);
+  if (e == hipSuccess) e = launch_reduce((const ReduceJob*)dj, (const Span*)ds, 4, a->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, a->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) {
+    set_error("fidelity: %s", hipGetErrorString(e));
+    return QAOA_EDEVICE;
+  }
+  *f_out = (h[0] * h[0] + h[1] * h[1]) / (h[2] * h[3]);
+  return QAOA_OK;
+}
+
+int qaoa_bind_stream(qaoa_ctx* c, void* hip_stream) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  if (c->dev_ready) HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->own_stream && c->stream) HIPCHK(hipStreamDestroy(c->stream));
+  c->stream = (hipStream_t)hip_stream;
+  c->own_stream = false;
+  c->stream_bound = true;
+  return QAOA_OK;
+}
+
+int qaoa_bind_state(qaoa_ctx* c, void* dev_ptr, size_t bytes) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  if (!dev_ptr || bytes != c->state_bytes || ((uintptr_t)dev_ptr & 255u)) {
+    set_error("state buffer must be %zu bytes, 256-byte aligned", c->state_bytes);
+    return QAOA_EINVAL;
+  }
+  if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->own_psi && c->psi) HIPCHK(hipFree(c->psi));
+  c->psi = dev_ptr;
+  c->own_psi = false;
+  c->have_state = c->have_expect = false;
+  return QAOA_OK;
+}
+
+int qaoa_set_profiling(qaoa_ctx* c, int enable) {
+  if (!c) {
+    set_error("context is NULL");
+    return QAOA_EINVAL;
+  }
+  c->profiling = enable != 0;
+  return QAOA_OK;
+}
+
+int qaoa_pass_times(qaoa_ctx* c, float* ms, double* bytes, int max, int* count) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  if (!count || max < 0) {
+    set_error("count is NULL");
+    return QAOA_EINVAL;
+  }
+  *count = c->ntimed;
+  if (c->ntimed == 0) return QAOA_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < c->ntimed && i < max; ++i) {
+    if (ms) HIPCHK(hipEventElapsedTime(&ms[i], c->ev[2 * i], c->ev[2 * i + 1]));
+    if (bytes) bytes[i] = c->pass_bytes[i];
+  }
+  return QAOA_OK;
+}
+
+int qaoa_plan_info(qaoa_ctx* c, int p, int* passes, int* sets, int* sizes, int max_sets) {
+  if (!c || p < 0) {
+    set_error("invalid arguments");
+    return QAOA_EINVAL;
+  }
+  const std::vector<SetGeom> s = make_sets(c->hg.n, prec_cfg(c->prec));
+  const std::vector<PassSpec> sch = make_schedule((int)s.size(), p);
+  if (passes) *passes = (int)sch.size();
+  if (sets) *sets = (int)s.size();
+  for (int i = 0; sizes && i < (int)s.size() && i < max_sets; ++i) sizes[i] = s[i].k;
+  return QAOA_OK;
+}
+
+int qaoa_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  if (!src || !dst || bytes == 0 || bytes % 16) {
+    set_error("copy probe needs non-NULL pointers and a multiple of 16 bytes");
+    return QAOA_EINVAL;
+  }
+  HIPCHK(launch_copy(src, dst, (int64_t)(bytes / 16), (hipStream_t)hip_stream));
+  return QAOA_OK;
+}
+
+}  // extern "C"

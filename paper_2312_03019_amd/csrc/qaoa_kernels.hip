@@ -1,0 +1,678 @@
+// gfx950 kernels of the QAOA max-cut state-vector simulator.
+//
+// Hot path (one launch per HBM pass, see qaoa_plan.h for the tile layout):
+//   k_forward  : load a tile (or synthesise |+>^n, launch control), run the
+//                pass's segments -- each an optional diagonal cost phase
+//                exp(-i gamma C(z)) (rotation compression, Eq. UC_opt /
+//                Algorithm 2, cut counted with Algorithm 3's popcount form
+//                for unweighted graphs) followed by exp(-i beta X_q) on the
+//                pass's qubits -- then optionally accumulate <C> and the norm
+//                in FP64, and store.
+//   k_backward : the adjoint sweep: undo a forward pass on (phi, lam) while
+//                accumulating Im<lam|X_q|phi> and Im<lam|C|phi> in FP64.
+// Support: k_reduce (deterministic second-stage sums), k_cut_table_*,
+// k_overlap (fidelity), k_copy (bandwidth reference).
+//
+// Design notes.  The state streams through each CU once per pass: every
+// amplitude is read and written exactly once, and all butterflies of the
+// pass happen in registers, with LDS used only to transpose which tile bits
+// are register bits.  The cost phase of a tile is never evaluated per
+// amplitude from scratch: each thread evaluates C at one index z0 (its
+// register bits zero) and, for each register bit k, the change d_k of the
+// cut when that bit flips alone; C(z0 ^ J) = C(z0) + sum_{k in J} d_k + RT[J]
+// with RT the cut among the register vertices (a per-pass table).  The
+// phase is then a product tree of 1 + LOGR complex exponentials.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qaoa_plan.h"
+#include "qaoa_launch.h"
+
+namespace qaoa {
+
+// Device memory reached through descriptors arrives as generic pointers;
+// state goes through the global address space (global_load/store), tables
+// and graph data through the constant space (scalar loads when uniform).
+// (The host pass only sees these bodies for the kernel stubs; it gets no
+// address spaces.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define QGLOBAL __attribute__((address_space(1)))
+#define QCONST __attribute__((address_space(4)))
+#else
+#define QGLOBAL
+#define QCONST
+#endif
+
+template <typename T>
+__device__ __forceinline__ QGLOBAL T* gmem(void* p) {
+  return (QGLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const QCONST T* cmem(const void* p) {
+  return (const QCONST T*)p;
+}
+
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+template <typename R>
+struct Prec;
+template <>
+struct Prec<float> {
+  static constexpr int kSwz = 5;   // 32 complex64 = 256 B per swizzle group
+  using V = float2;
+};
+template <>
+struct Prec<double> {
+  static constexpr int kSwz = 4;   // 16 complex128 = 256 B per swizzle group
+  using V = double2;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> ldg(const QGLOBAL cx<R>* p) {
+  const typename Prec<R>::V v = *reinterpret_cast<const QGLOBAL typename Prec<R>::V*>(p);
+  return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void stg(QGLOBAL cx<R>* p, cx<R> a) {
+  typename Prec<R>::V v;
+  v.x = a.re;
+  v.y = a.im;
+  *reinterpret_cast<QGLOBAL typename Prec<R>::V*>(p) = v;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {  // a * conj(b)
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+
+// LDS index swizzle: XOR-fold the higher groups of the tile index into the
+// lowest group.  GF(2)-linear and a bijection on the tile.
+template <typename R>
+__device__ __forceinline__ uint32_t swz(uint32_t t) {
+  constexpr int G = Prec<R>::kSwz;
+  constexpr uint32_t M = (1u << G) - 1u;
+  return t ^ (((t >> G) ^ (t >> (2 * G)) ^ (t >> (3 * G))) & M);
+}
+
+// Tile index of (thread tid, register 0) in a round whose register bits are [b, b+LOGR).
+template <int LOGR>
+__device__ __forceinline__ uint32_t tbase(uint32_t tid, int b) {
+  return (tid & ((1u << b) - 1u)) | ((tid >> b) << (b + LOGR));
+}
+
+// Tile index -> memory offset: tile bits [0,L) stay, tile bits [L,K) go to [h, h+K-L).
+__device__ __forceinline__ uint64_t tmem(uint32_t t, int L, int h) {
+  return (uint64_t)(t & ((1u << L) - 1u)) | ((uint64_t)(t >> L) << h);
+}
+
+// Memory offset of register index j in a round with register base b.
+template <int LOGR>
+__device__ __forceinline__ uint64_t moff(int j, int b, int L, int h) {
+  return tmem((uint32_t)j << b, L, h);
+}
+
+template <typename R, int LOGR>
+__device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const QGLOBAL cx<R>* __restrict__ src,
+                                          uint64_t zt, int b, int L, int h) {
+  const QGLOBAL cx<R>* base = src + zt;
+#pragma unroll
+  for (int j = 0; j < (1 << LOGR); ++j) v[j] = ldg(base + moff<LOGR>(j, b, L, h));
+}
+
+template <typename R, int LOGR>
+__device__ __forceinline__ void store_tile(const cx<R> (&v)[1 << LOGR], QGLOBAL cx<R>* __restrict__ dst,
+                                           uint64_t zt, int b, int L, int h) {
+  QGLOBAL cx<R>* base = dst + zt;
+#pragma unroll
+  for (int j = 0; j < (1 << LOGR); ++j) stg(base + moff<LOGR>(j, b, L, h), v[j]);
+}
+
+// Move the register contents from round mapping `from` to round mapping `to` through LDS.
+template <typename R, int LOGR>
+__device__ __forceinline__ void transpose(cx<R>* lds, cx<R> (&v)[1 << LOGR], uint32_t tid,
+                                          int from, int to) {
+  const uint32_t s0 = swz<R>(tbase<LOGR>(tid, from));
+#pragma unroll
+  for (int j = 0; j < (1 << LOGR); ++j) lds[s0 ^ swz<R>((uint32_t)j << from)] = v[j];
+  __syncthreads();
+  const uint32_t s1 = swz<R>(tbase<LOGR>(tid, to));
+#pragma unroll
+  for (int j = 0; j < (1 << LOGR); ++j) v[j] = lds[s1 ^ swz<R>((uint32_t)j << to)];
+  __syncthreads();
+}
+
+// exp(-i beta X) on a pair (a, b) = amplitudes differing only in that qubit.
+template <typename R>
+__device__ __forceinline__ void bfly(cx<R>& a, cx<R>& b, R c, R s) {
+  const cx<R> A = a, B = b;
+  a.re = c * A.re + s * B.im;
+  a.im = c * A.im - s * B.re;
+  b.re = c * B.re + s * A.im;
+  b.im = c * B.im - s * A.re;
+}
+
+template <typename R, int LOGR>
+__device__ __forceinline__ void rx_regs(cx<R> (&v)[1 << LOGR], int mask, R c, R s) {
+#pragma unroll
+  for (int k = 0; k < LOGR; ++k) {
+    if (mask & (1 << k)) {
+#pragma unroll
+      for (int j = 0; j < (1 << LOGR); ++j)
+        if (!(j & (1 << k))) bfly(v[j], v[j | (1 << k)], c, s);
+    }
+  }
+}
+
+// exp(-i th) in the working precision.  Single precision: reduce th modulo
+// 2 pi in double (two-constant Cody-Waite) before the float sine/cosine.
+template <typename R>
+__device__ __forceinline__ cx<R> expmi(double th);
+template <>
+__device__ __forceinline__ cx<double> expmi<double>(double th) {
+  double s, c;
+  sincos(th, &s, &c);
+  return {c, -s};
+}
+template <>
+__device__ __forceinline__ cx<float> expmi<float>(double th) {
+  const double k = rint(th * 0.15915494309189535);
+  double r = fma(-k, 6.283185307179586, th);
+  r = fma(-k, 2.4492935982947064e-16, r);
+  float s, c;
+  sincosf((float)r, &s, &c);
+  return {c, -s};
+}
+
+struct SiteVals {
+  double cz0;
+  double d[kMaxLogR];
+};
+
+// C(z0) and, for each register bit k, the cut change when only vertex q_k
+// flips from 0 to 1 (edges to other register vertices excluded).
+template <int LOGR>
+__device__ SiteVals site_values(const QCONST GraphDev* __restrict__ g, const SiteDesc& S, uint64_t z0) {
+  SiteVals r;
+  const int n = g->n;
+  if (!g->weighted) {
+    int c = 0;
+    for (int v = 0; v < n; ++v) {
+      const uint64_t bI = 0ull - ((z0 >> v) & 1ull);      // b_I of Algorithm 3
+      c += __popcll(g->upper[v] & (bI ^ z0));
+    }
+    r.cz0 = (double)c;
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) {
+      const uint64_t ax = g->adj[S.q[k]] & ~S.qmask;
+      r.d[k] = (double)(__popcll(ax) - 2 * __popcll(ax & z0));
+    }
+  } else {
+    double c = 0.0;
+    const int m = g->m;
+    const QCONST int32_t* eu = cmem<int32_t>(g->eu);
+    const QCONST int32_t* ev = cmem<int32_t>(g->ev);
+    const QCONST double* ew = cmem<double>(g->ew);
+    for (int e = 0; e < m; ++e)
+      if (((z0 >> eu[e]) ^ (z0 >> ev[e])) & 1ull) c += ew[e];
+    r.cz0 = c;
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) {
+      const int q = S.q[k];
+      double d = 0.0;
+      const QCONST int32_t* nbr = cmem<int32_t>(g->nbr);
+      const QCONST double* nw = cmem<double>(g->nw);
+      for (int i = g->off[q]; i < g->off[q + 1]; ++i) {
+        const int v = nbr[i];
+        if (!((S.qmask >> v) & 1ull)) d += ((z0 >> v) & 1ull) ? -nw[i] : nw[i];
+      }
+      r.d[k] = d;
+    }
+  }
+#pragma unroll
+  for (int k = LOGR; k < kMaxLogR; ++k) r.d[k] = 0.0;
+  return r;
+}
+
+// v[J] *= exp(-i gamma C(z0 ^ J)), or its conjugate when `undo`.  The
+// per-amplitude phase is exp(-i gamma C(z0)) * prod_{k in J} exp(-i gamma d_k)
+// * exp(-i gamma RT[J]); the product over J is split into a low and a high
+// half-tree so only 2^3 + 2^(LOGR-3) partial products stay in registers.
+template <typename R, int LOGR>
+__device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVals& sv, double gamma,
+                                            const QCONST cx<R>* __restrict__ rtph, bool undo) {
+  constexpr int LO = LOGR < 3 ? LOGR : 3;
+  constexpr int HI = LOGR - LO;
+  const double gs = undo ? -gamma : gamma;
+  cx<R> plo[1 << LO], phi[1 << HI];
+  plo[0] = expmi<R>(gs * sv.cz0);
+#pragma unroll
+  for (int k = 0; k < LO; ++k) {
+    const cx<R> e = expmi<R>(gs * sv.d[k]);
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) plo[j | (1 << k)] = cmul(plo[j], e);
+  }
+  phi[0] = {(R)1, (R)0};
+#pragma unroll
+  for (int k = 0; k < HI; ++k) {
+    const cx<R> e = expmi<R>(gs * sv.d[LO + k]);
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) phi[j | (1 << k)] = cmul(phi[j], e);
+  }
+#pragma unroll
+  for (int j = 0; j < (1 << LOGR); ++j) {
+    const cx<R> rt = rtph[j];
+    const cx<R> t = undo ? cmulc(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt)
+                         : cmul(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt);
+    v[j] = cmul(v[j], t);
+  }
+}
+
+// Sum over the 64-lane wave, then across waves; result valid on thread 0.
+__device__ __forceinline__ void block_reduce2(double& a, double& b, double* red, int nthreads) {
+  const int wsz = nthreads < 64 ? nthreads : 64;
+  for (int off = wsz >> 1; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, wsz);
+    b += __shfl_xor(b, off, wsz);
+  }
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) {
+    red[2 * (tid >> 6)] = a;
+    red[2 * (tid >> 6) + 1] = b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a = 0.0;
+    b = 0.0;
+    for (int w = 0; w < (nthreads + 63) / 64; ++w) {
+      a += red[2 * w];
+      b += red[2 * w + 1];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int find_desc(const PassDesc* __restrict__ descs, int ndesc, int64_t wg) {
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= wg) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
+  const int lowfree = D.h - D.L;
+  return (((uint64_t)g & ((1ull << lowfree) - 1ull)) << D.L) |
+         (((uint64_t)g >> lowfree) << (D.h + D.K - D.L));
+}
+
+template <typename R, int LOGR, int KB>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) k_forward(const PassDesc* __restrict__ descs, int ndesc) {
+  constexpr int NR = 1 << LOGR;
+  __shared__ cx<R> lds[1 << KB];
+  __shared__ double red[2 * (kMaxThreads / 64)];
+  const uint32_t tid = threadIdx.x;
+  const int64_t wg = blockIdx.x;
+  const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, wg) : 0];
+  const int64_t g = wg - D.tile_begin;
+  const int L = D.L, h = D.h, nr = D.nrounds;
+  const uint64_t zbase = tile_zbase(D, g);
+  QGLOBAL cx<R>* __restrict__ psi = gmem<cx<R>>(D.psi);
+  const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
+  const QCONST GraphDev* __restrict__ gr = cmem<GraphDev>(D.g);
+  const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
+
+  const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
+  cx<R> v[NR];
+  if (D.flags & PF_GEN) {
+    const R a = (R)D.amp0;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = {a, (R)0};
+  } else {
+    load_tile<R, LOGR>(v, psi, zt0, D.rb[0], L, h);
+  }
+
+  SiteVals sv0{}, sv1{};
+  if (D.flags & PF_SITE0) sv0 = site_values<LOGR>(gr, D.site[0], zt0);
+  if (D.flags & PF_SITE1)
+    sv1 = site_values<LOGR>(gr, D.site[1], zbase | tmem(tbase<LOGR>(tid, D.rb[nr - 1]), L, h));
+
+  int cur = 0;
+  for (int s = 0; s < D.nseg; ++s) {
+    const SegDesc sg = segs[s];
+    if (sg.has_phase) apply_phase<R, LOGR>(v, (s & 1) ? sv1 : sv0, sg.gamma, ctab + sg.ph_off, false);
+    const R c = (R)sg.cb, sn = (R)sg.sb;
+    if (!(s & 1)) {
+      for (int i = 0; i < nr; ++i) {
+        if (i != cur) {
+          transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[i]);
+          cur = i;
+        }
+        rx_regs<R, LOGR>(v, D.rxmask[i], c, sn);
+      }
+    } else {
+      for (int i = nr - 1; i >= 0; --i) {
+        if (i != cur) {
+          transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[i]);
+          cur = i;
+        }
+        rx_regs<R, LOGR>(v, D.rxmask[i], c, sn);
+      }
+    }
+  }
+  if (cur != 0) transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[0]);
+
+  if (D.flags & PF_EXPECT) {
+    // Gray-code walk over the register index: one FP64 add per amplitude.
+    const QCONST double* __restrict__ rt = cmem<double>(D.dtab) + D.site[0].rt_off;
+    QGLOBAL cx<R>* __restrict__ lam = gmem<cx<R>>(D.lam) + zt0;
+    const bool wl = (D.flags & PF_WRITE_LAM) != 0;
+    double aE = 0.0, aN = 0.0, c = sv0.cz0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int J = i ^ (i >> 1);
+      if (i > 0) {
+        const int k = __builtin_ctz(i);
+        c += ((J >> k) & 1) ? sv0.d[k] : -sv0.d[k];
+      }
+      const double cj = c + rt[J];
+      const double pr = (double)v[J].re * v[J].re + (double)v[J].im * v[J].im;
+      aE = fma(pr, cj, aE);
+      aN += pr;
+      if (wl) {
+        const cx<R> lv = {(R)(cj * v[J].re), (R)(cj * v[J].im)};
+        stg(lam + moff<LOGR>(J, D.rb[0], L, h), lv);
+      }
+    }
+    block_reduce2(aE, aN, red, blockDim.x);
+    if (tid == 0) {
+      QGLOBAL double* part = gmem<double>(D.part);
+      part[g] = aE;
+      part[D.ntiles + g] = aN;
+    }
+  }
+  if (!(D.flags & PF_NO_STORE)) store_tile<R, LOGR>(v, psi, zt0, D.rb[0], L, h);
+}
+
+// Im sum over register pairs of conj(l_a) f_b + conj(l_b) f_a, for the qubits in mask.
+template <typename R, int LOGR>
+__device__ __forceinline__ double dbeta_round(const cx<R> (&f)[1 << LOGR], const cx<R> (&l)[1 << LOGR],
+                                              int mask) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < LOGR; ++k) {
+    if (mask & (1 << k)) {
+      R a = (R)0;
+#pragma unroll
+      for (int j = 0; j < (1 << LOGR); ++j) {
+        if (!(j & (1 << k))) {
+          const int b = j | (1 << k);
+          a += l[j].re * f[b].im - l[j].im * f[b].re + l[b].re * f[j].im - l[b].im * f[j].re;
+        }
+      }
+      acc += (double)a;
+    }
+  }
+  return acc;
+}
+
+template <typename R, int LOGR, int KB>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) k_backward(const PassDesc* __restrict__ descs, int ndesc) {
+  constexpr int NR = 1 << LOGR;
+  __shared__ cx<R> lds[1 << KB];
+  __shared__ double red[2 * (kMaxThreads / 64)];
+  const uint32_t tid = threadIdx.x;
+  const int64_t wg = blockIdx.x;
+  const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, wg) : 0];
+  const int64_t g = wg - D.tile_begin;
+  const int L = D.L, h = D.h, nr = D.nrounds, nseg = D.nseg;
+  const int64_t nt = D.ntiles;
+  const uint64_t zbase = tile_zbase(D, g);
+  QGLOBAL cx<R>* __restrict__ phi = gmem<cx<R>>(D.psi);
+  QGLOBAL cx<R>* __restrict__ lamp = gmem<cx<R>>(D.lam);
+  QGLOBAL double* __restrict__ part = gmem<double>(D.part);
+  const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
+  const QCONST GraphDev* __restrict__ gr = cmem<GraphDev>(D.g);
+  const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
+
+  const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
+  cx<R> f[NR], l[NR];
+  load_tile<R, LOGR>(f, phi, zt0, D.rb[0], L, h);
+  load_tile<R, LOGR>(l, lamp, zt0, D.rb[0], L, h);
+
+  SiteVals sv0{}, sv1{};
+  if (D.flags & PF_SITE0) sv0 = site_values<LOGR>(gr, D.site[0], zt0);
+  if (D.flags & PF_SITE1)
+    sv1 = site_values<LOGR>(gr, D.site[1], zbase | tmem(tbase<LOGR>(tid, D.rb[nr - 1]), L, h));
+
+  int cur = 0;
+  if ((nseg & 1) && nr > 1) {
+    transpose<R, LOGR>(lds, f, tid, D.rb[0], D.rb[nr - 1]);
+    transpose<R, LOGR>(lds, l, tid, D.rb[0], D.rb[nr - 1]);
+    cur = nr - 1;
+  }
+  for (int s = nseg - 1; s >= 0; --s) {
+    const SegDesc sg = segs[s];
+    const R c = (R)sg.cb, sn = (R)(-sg.sb);  // exp(+i beta X) undoes the mixer
+    double dB = 0.0;
+    const bool fwd_even = !(s & 1);
+    for (int t = 0; t < nr; ++t) {
+      const int i = fwd_even ? nr - 1 - t : t;
+      if (i != cur) {
+        transpose<R, LOGR>(lds, f, tid, D.rb[cur], D.rb[i]);
+        transpose<R, LOGR>(lds, l, tid, D.rb[cur], D.rb[i]);
+        cur = i;
+      }
+      dB += dbeta_round<R, LOGR>(f, l, D.rxmask[i]);
+      rx_regs<R, LOGR>(f, D.rxmask[i], c, sn);
+      rx_regs<R, LOGR>(l, D.rxmask[i], c, sn);
+    }
+    double zero = 0.0;
+    block_reduce2(dB, zero, red, blockDim.x);
+    if (tid == 0) part[(int64_t)(2 * s) * nt + g] = dB;
+    if (sg.has_phase) {
+      const SiteVals& sv = (s & 1) ? sv1 : sv0;
+      const QCONST double* __restrict__ rt = cmem<double>(D.dtab) + D.site[s & 1].rt_off;
+      double dG = 0.0, c0 = sv.cz0;
+#pragma unroll
+      for (int ii = 0; ii < NR; ++ii) {
+        const int J = ii ^ (ii >> 1);
+        if (ii > 0) {
+          const int k = __builtin_ctz(ii);
+          c0 += ((J >> k) & 1) ? sv.d[k] : -sv.d[k];
+        }
+        const R im = l[J].re * f[J].im - l[J].im * f[J].re;   // Im(conj(l) f)
+        dG = fma(c0 + rt[J], (double)im, dG);
+      }
+      block_reduce2(dG, zero, red, blockDim.x);
+      if (tid == 0) part[(int64_t)(2 * s + 1) * nt + g] = dG;
+      if (!((D.flags & PF_NO_STORE) && s == 0)) {
+        apply_phase<R, LOGR>(f, sv, sg.gamma, ctab + sg.ph_off, true);
+        apply_phase<R, LOGR>(l, sv, sg.gamma, ctab + sg.ph_off, true);
+      }
+    }
+  }
+  if (!(D.flags & PF_NO_STORE)) {
+    if (cur != 0) {
+      transpose<R, LOGR>(lds, f, tid, D.rb[cur], D.rb[0]);
+      transpose<R, LOGR>(lds, l, tid, D.rb[cur], D.rb[0]);
+    }
+    store_tile<R, LOGR>(f, phi, zt0, D.rb[0], L, h);
+    store_tile<R, LOGR>(l, lamp, zt0, D.rb[0], L, h);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic second-stage sums: one workgroup per output, Neumaier
+// compensation per thread over a fixed stride, then a fixed-order combine.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void nadd(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+__global__ void __launch_bounds__(256) k_reduce(const ReduceJob* __restrict__ jobs, const Span* __restrict__ spans) {
+  __shared__ double ss[256], cc[256];
+  const ReduceJob J = jobs[blockIdx.x];
+  double s = 0.0, c = 0.0;
+  for (int k = J.span_begin; k < J.span_end; ++k) {
+    const Span sp = spans[k];
+    const QGLOBAL double* p = (const QGLOBAL double*)sp.ptr;
+    for (int64_t i = threadIdx.x; i < sp.count; i += 256) nadd(s, c, p[i]);
+  }
+  ss[threadIdx.x] = s;
+  cc[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ts = 0.0, tc = 0.0;
+    for (int i = 0; i < 256; ++i) {
+      nadd(ts, tc, ss[i]);
+      nadd(ts, tc, cc[i]);
+    }
+    *(QGLOBAL double*)J.out = J.scale * (ts + tc);
+  }
+}
+
+// Cut values, unweighted: Algorithm 3's popcount count of cut edges.
+__global__ void k_cut_table_i32(const GraphDev* __restrict__ gp, int32_t* __restrict__ out, int64_t N) {
+  const QCONST GraphDev* g = cmem<GraphDev>(gp);
+  const int n = g->n;
+  for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < N; z += (int64_t)gridDim.x * blockDim.x) {
+    int c = 0;
+    const uint64_t b = (uint64_t)z;
+    for (int v = 0; v < n; ++v) c += __popcll(g->upper[v] & ((0ull - ((b >> v) & 1ull)) ^ b));
+    out[z] = c;
+  }
+}
+
+// Cut values, weighted: FP64 sum over cut edges in canonical edge order.
+__global__ void k_cut_table_f64(const GraphDev* __restrict__ gp, double* __restrict__ out, int64_t N) {
+  const QCONST GraphDev* g = cmem<GraphDev>(gp);
+  const int m = g->m;
+  const QCONST int32_t* eu = cmem<int32_t>(g->eu);
+  const QCONST int32_t* ev = cmem<int32_t>(g->ev);
+  const QCONST double* ew = cmem<double>(g->ew);
+  for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < N; z += (int64_t)gridDim.x * blockDim.x) {
+    double c = 0.0;
+    const uint64_t b = (uint64_t)z;
+    for (int e = 0; e < m; ++e)
+      if (((b >> eu[e]) ^ (b >> ev[e])) & 1ull) c += ew[e];
+    out[z] = c;
+  }
+}
+
+// Per-block partials of Re<a|b>, Im<a|b>, <a|a>, <b|b> in FP64 (fixed grid).
+template <typename Ra, typename Rb>
+__global__ void __launch_bounds__(256) k_overlap(const cx<Ra>* __restrict__ a, const cx<Rb>* __restrict__ b,
+                                                 int64_t N, double* __restrict__ part) {
+  __shared__ double red[2 * 4];
+  double sr = 0.0, si = 0.0, sa = 0.0, sb = 0.0;
+  for (int64_t z = (int64_t)blockIdx.x * 256 + threadIdx.x; z < N; z += (int64_t)gridDim.x * 256) {
+    const cx<Ra> x = ldg((const QGLOBAL cx<Ra>*)(a + z));
+    const cx<Rb> y = ldg((const QGLOBAL cx<Rb>*)(b + z));
+    const double ar = x.re, ai = x.im, br = y.re, bi = y.im;
+    sr += ar * br + ai * bi;
+    si += ar * bi - ai * br;
+    sa += ar * ar + ai * ai;
+    sb += br * br + bi * bi;
+  }
+  block_reduce2(sr, si, red, 256);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sr;
+    part[gridDim.x + blockIdx.x] = si;
+  }
+  block_reduce2(sa, sb, red, 256);
+  if (threadIdx.x == 0) {
+    part[2 * gridDim.x + blockIdx.x] = sa;
+    part[3 * gridDim.x + blockIdx.x] = sb;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s, float4* __restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) d[i] = s[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename R, int KB>
+static hipError_t launch_pass_t(bool backward, int logr, const PassDesc* d, int ndesc, int64_t nblocks,
+                                int nthreads, hipStream_t st) {
+  const dim3 grid((unsigned)nblocks), block((unsigned)nthreads);
+#define QAOA_CASE(LR)                                                                  \
+  case LR:                                                                             \
+    if (backward) hipLaunchKernelGGL((k_backward<R, LR, KB>), grid, block, 0, st, d, ndesc); \
+    else hipLaunchKernelGGL((k_forward<R, LR, KB>), grid, block, 0, st, d, ndesc);   \
+    break;
+  switch (logr) {
+    QAOA_CASE(1)
+    QAOA_CASE(2)
+    QAOA_CASE(3)
+    QAOA_CASE(4)
+    case 5:
+      if constexpr (sizeof(R) == 4) {
+        if (backward) hipLaunchKernelGGL((k_backward<R, 5, KB>), grid, block, 0, st, d, ndesc);
+        else hipLaunchKernelGGL((k_forward<R, 5, KB>), grid, block, 0, st, d, ndesc);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef QAOA_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(int prec, bool backward, int logr, const PassDesc* d, int ndesc, int64_t nblocks,
+                       int nthreads, hipStream_t st) {
+  if (prec == 1) return launch_pass_t<float, kTileBitsC64>(backward, logr, d, ndesc, nblocks, nthreads, st);
+  return launch_pass_t<double, kTileBitsC128>(backward, logr, d, ndesc, nblocks, nthreads, st);
+}
+
+hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(njobs), dim3(256), 0, st, jobs, spans);
+  return hipGetLastError();
+}
+
+hipError_t launch_cut_table(const GraphDev* g, bool weighted, void* out, int64_t N, hipStream_t st) {
+  const int64_t blocks64 = (N + 255) / 256;
+  const unsigned blocks = (unsigned)(blocks64 < 65536 ? blocks64 : 65536);
+  if (weighted) hipLaunchKernelGGL(k_cut_table_f64, dim3(blocks), dim3(256), 0, st, g, (double*)out, N);
+  else hipLaunchKernelGGL(k_cut_table_i32, dim3(blocks), dim3(256), 0, st, g, (int32_t*)out, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, int64_t N, double* part,
+                          int nblocks, hipStream_t st) {
+  const dim3 grid(nblocks), block(256);
+  if (prec_a == 1 && prec_b == 1)
+    hipLaunchKernelGGL((k_overlap<float, float>), grid, block, 0, st, (const cx<float>*)a, (const cx<float>*)b, N, part);
+  else if (prec_a == 1)
+    hipLaunchKernelGGL((k_overlap<float, double>), grid, block, 0, st, (const cx<float>*)a, (const cx<double>*)b, N, part);
+  else if (prec_b == 1)
+    hipLaunchKernelGGL((k_overlap<double, float>), grid, block, 0, st, (const cx<double>*)a, (const cx<float>*)b, N, part);
+  else
+    hipLaunchKernelGGL((k_overlap<double, double>), grid, block, 0, st, (const cx<double>*)a, (const cx<double>*)b, N, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st) {
+  int64_t blocks = (n16 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src, (float4*)dst, n16);
+  return hipGetLastError();
+}
+
+}  // namespace qaoa

@@ -1,0 +1,28 @@
+// Host-side launchers of the gfx950 kernels (defined in qaoa_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qaoa_plan.h"
+
+namespace qaoa {
+
+// Tile bits per precision: 2^13 complex64 = 2^12 complex128 = 64 KiB of LDS.
+constexpr int kTileBitsC64 = 13;
+constexpr int kTileBitsC128 = 12;
+constexpr int kLogRC64 = 5;     // 32 amplitudes per thread
+constexpr int kLogRC128 = 4;    // 16 amplitudes per thread
+constexpr int kPassengerC64 = 4;   // high passes keep >= 16 contiguous complex64 (128 B)
+constexpr int kPassengerC128 = 3;  // ... >= 8 contiguous complex128 (128 B)
+
+// prec: 1 = complex64, 0 = complex128.  One workgroup per tile; descriptors
+// are found by tile_begin when ndesc > 1.
+hipError_t launch_pass(int prec, bool backward, int logr, const PassDesc* d, int ndesc, int64_t nblocks,
+                       int nthreads, hipStream_t st);
+hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hipStream_t st);
+hipError_t launch_cut_table(const GraphDev* g, bool weighted, void* out, int64_t N, hipStream_t st);
+hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, int64_t N, double* part,
+                          int nblocks, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
+
+}  // namespace qaoa

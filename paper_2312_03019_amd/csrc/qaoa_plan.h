@@ -1,0 +1,93 @@
+// Work descriptors shared by the host runtime and the gfx950 pass kernels.
+//
+// A run is a list of HBM passes.  Each pass streams the whole state through
+// on-chip memory one tile at a time: a tile is 2^K amplitudes whose indices
+// differ in a fixed set of K bits (the "tile bits"), the rest of the index
+// (the tile id) being fixed.  Tile bits [0, L) are memory bits [0, L)
+// (contiguous, so loads coalesce); tile bits [L, K) are memory bits
+// [h, h + K - L).  Inside the tile, each thread holds 2^LOGR amplitudes in
+// registers whose indices differ in LOGR consecutive tile bits [b, b + LOGR)
+// (a "round"); LDS transposes move from one round's register bits to the
+// next.  The mixer qubits of a pass are applied round by round.
+#pragma once
+#include <stdint.h>
+
+namespace qaoa {
+
+enum : int32_t {
+  PF_GEN = 1,         // generate |+>^n in registers instead of loading
+  PF_EXPECT = 2,      // accumulate <C> and norm partials after the last segment
+  PF_WRITE_LAM = 4,   // forward: also store lam = C psi (start of the adjoint sweep)
+  PF_NO_STORE = 8,    // backward: state is not written back (undoing the first pass)
+  PF_SITE0 = 16,      // per-thread cut values needed at the round-0 mapping
+  PF_SITE1 = 32,      // ... and at the last round's mapping
+};
+
+constexpr int kMaxLogR = 5;
+constexpr int kMaxRounds = 4;
+constexpr int kMaxN = 34;
+constexpr int kMaxThreads = 256;
+
+// Graph in device memory.  Masks hold one bit per vertex.
+struct GraphDev {
+  int32_t n, m, weighted, pad;
+  uint64_t adj[kMaxN];      // all neighbours of v
+  uint64_t upper[kMaxN];    // neighbours j > v (graph_I of Algorithm 3)
+  int32_t off[kMaxN + 2];   // CSR row offsets into nbr/nw
+  const int32_t *eu;        // edge endpoints (canonical order), weighted cut sum
+  const int32_t *ev;
+  const double *ew;
+  const int32_t *nbr;       // CSR neighbour lists
+  const double *nw;
+};
+
+// Where the cost phase / cut value is evaluated: the register mapping of one
+// round.  q[k] is the memory bit (vertex) carried by register bit k.
+struct SiteDesc {
+  uint64_t qmask;
+  int32_t q[kMaxLogR];
+  int32_t rt_off;           // offset (doubles) into dtab of the 2^LOGR internal-cut values
+};
+
+// One segment = optional cost phase exp(-i gamma C) then the mixer on the
+// pass's qubit set.  Segments alternate their round order.
+struct SegDesc {
+  double gamma, beta;
+  double cb, sb;            // cos(beta), sin(beta) in FP64
+  int32_t has_phase;
+  int32_t ph_off;           // offset (complex elements) into ctab of exp(-i gamma RT[J])
+};
+
+struct PassDesc {
+  void *psi;                // state (complex, working precision)
+  void *lam;                // adjoint vector (gradient only)
+  const GraphDev *g;
+  const double *dtab;       // FP64 tables of this descriptor's run
+  const void *ctab;         // complex tables (working precision)
+  const SegDesc *segs;      // this pass's segments
+  double *part;             // partial-sum slots: part[slot * ntiles + tile]
+  int64_t tile_begin;       // first workgroup of this descriptor within the launch
+  int64_t ntiles;
+  int32_t n, K, L, h;
+  int32_t nrounds;
+  int32_t rb[kMaxRounds];   // register-bit base of each round
+  int32_t rxmask[kMaxRounds];  // which register bits get the mixer in that round
+  int32_t flags;
+  int32_t nseg;
+  SiteDesc site[2];         // site 0: mapping of round 0; site 1: of the last round
+  double amp0;              // 2^(-n/2)
+};
+
+// One output value: *out = scale * (sum of the listed spans, in order).
+struct ReduceJob {
+  int32_t span_begin, span_end;  // into the span array
+  double scale;
+  double *out;
+};
+
+struct Span {
+  const double *ptr;   // partial sums (device)
+  int64_t count;
+};
+
+}  // namespace qaoa

