@@ -371,7 +371,7 @@ int qaoa_fidelity(qaoa_ctx* a, qaoa_ctx* b, double* f_out) {
   const size_t part_b = 4 * (size_t)nb * sizeof(double);
   const size_t total = part_b + 4 * sizeof(ReduceJob) + 4 * sizeof(Span) + 4 * sizeof(double) + 256;
   char* d = nullptr;
-  HIPCHK(hipMalloc(&d, total));
+  HIPCHK(hipMalloc((void**)&d, total));
   char* dj = d + part_b;
   char* ds = dj + 4 * sizeof(ReduceJob);
   double* dout = (double*)(ds + 4 * sizeof(Span));

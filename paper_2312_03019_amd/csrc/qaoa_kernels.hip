@@ -205,13 +205,14 @@ __device__ SiteVals site_values(const QCONST GraphDev* __restrict__ g, const Sit
     int c = 0;
     for (int v = 0; v < n; ++v) {
       const uint64_t bI = 0ull - ((z0 >> v) & 1ull);      // b_I of Algorithm 3
-      c += __popcll(g->upper[v] & (bI ^ z0));
+      c += (int)__popcll(g->upper[v] & (bI ^ z0));
     }
     r.cz0 = (double)c;
 #pragma unroll
     for (int k = 0; k < LOGR; ++k) {
       const uint64_t ax = g->adj[S.q[k]] & ~S.qmask;
-      r.d[k] = (double)(__popcll(ax) - 2 * __popcll(ax & z0));
+      // __popcll is unsigned: form the signed difference explicitly
+      r.d[k] = (double)((int)__popcll(ax) - 2 * (int)__popcll(ax & z0));
     }
   } else {
     double c = 0.0;
@@ -550,7 +551,7 @@ __global__ void k_cut_table_i32(const GraphDev* __restrict__ gp, int32_t* __rest
   for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < N; z += (int64_t)gridDim.x * blockDim.x) {
     int c = 0;
     const uint64_t b = (uint64_t)z;
-    for (int v = 0; v < n; ++v) c += __popcll(g->upper[v] & ((0ull - ((b >> v) & 1ull)) ^ b));
+    for (int v = 0; v < n; ++v) c += (int)__popcll(g->upper[v] & ((0ull - ((b >> v) & 1ull)) ^ b));
     out[z] = c;
   }
 }

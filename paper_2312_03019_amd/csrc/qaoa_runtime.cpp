@@ -401,19 +401,22 @@ ImageLayout image_layout(const RunImage& img, int prec) {
 void pack_run(RunImage& img, const ImageLayout& lay, int prec, void* host_buf, char* dev_region, double* part,
               double* out) {
   char* h = (char*)host_buf;
-  memcpy(h + lay.off_segs, img.segs.data(), img.segs.size() * sizeof(SegDesc));
-  memcpy(h + lay.off_dtab, img.dtab.data(), img.dtab.size() * sizeof(double));
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) memcpy(h + off, src, bytes);
+  };
+  put(lay.off_segs, img.segs.data(), img.segs.size() * sizeof(SegDesc));
+  put(lay.off_dtab, img.dtab.data(), img.dtab.size() * sizeof(double));
   const size_t nc = img.ctab.size() / 2;
   if (prec == QAOA_C64) {
     float* c = (float*)(h + lay.off_ctab);
     for (size_t i = 0; i < 2 * nc; ++i) c[i] = (float)img.ctab[i];
   } else {
-    memcpy(h + lay.off_ctab, img.ctab.data(), 2 * nc * sizeof(double));
+    put(lay.off_ctab, img.ctab.data(), 2 * nc * sizeof(double));
   }
   for (auto& j : img.jobs) j.out = out + (intptr_t)j.out;
   for (auto& sp : img.spans) sp.ptr = part + (intptr_t)sp.ptr;
-  memcpy(h + lay.off_jobs, img.jobs.data(), img.jobs.size() * sizeof(ReduceJob));
-  memcpy(h + lay.off_spans, img.spans.data(), img.spans.size() * sizeof(Span));
+  put(lay.off_jobs, img.jobs.data(), img.jobs.size() * sizeof(ReduceJob));
+  put(lay.off_spans, img.spans.data(), img.spans.size() * sizeof(Span));
   auto patch = [&](PassDesc& d) {
     const intptr_t seg0 = (intptr_t)d.segs;
     d.segs = (const SegDesc*)(dev_region + lay.off_segs) + seg0;
@@ -423,8 +426,8 @@ void pack_run(RunImage& img, const ImageLayout& lay, int prec, void* host_buf, c
   };
   for (auto& d : img.fwd) patch(d);
   for (auto& d : img.bwd) patch(d);
-  memcpy(h + lay.off_fwd, img.fwd.data(), img.fwd.size() * sizeof(PassDesc));
-  memcpy(h + lay.off_bwd, img.bwd.data(), img.bwd.size() * sizeof(PassDesc));
+  put(lay.off_fwd, img.fwd.data(), img.fwd.size() * sizeof(PassDesc));
+  put(lay.off_bwd, img.bwd.data(), img.bwd.size() * sizeof(PassDesc));
 }
 
 }  // namespace qaoa
