@@ -111,9 +111,27 @@ def serve_bench(q, W, nreq):
     return out
 
 
+def copy_ceiling(q, torch, nbytes=4 << 30, reps=5):
+    """Device-to-device streaming copy with the library's probe kernel (GB/s, read + write)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    q.qaoa_copy_probe(src, dst, nbytes, st)
+    st.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        q.qaoa_copy_probe(src, dst, nbytes, st)
+    b.record(st)
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(W):
     import oracle
-    n, p = 26, 2
+    n, p = 28, 5
     rng = W.SplitMix64(3)
     e = W.random_regular(n, 3, rng)
     w = W.uniform_weights(e.shape[0], rng)
@@ -155,6 +173,8 @@ def main():
     del keep64
     torch.cuda.empty_cache()
 
+    copy_gbs = copy_ceiling(q, torch)
+    torch.cuda.empty_cache()
     r64 = res["c64"]
     ms, by = np.array(r64["pass_ms"]), np.array(r64["pass_bytes"])
     achieved = by.sum() / (ms.sum() * 1e-3) / 1e9          # GB/s, average over the run's launches
@@ -183,6 +203,7 @@ def main():
     line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                         "kernel": "k_forward (one launch per HBM pass)",
+                        "copy_ceiling_gbps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                         "per_launch_bytes": "2*2^n*8 (write-only 2^n*8 for the first pass)"}
     if not a.no_serve:
         line["serve"] = serve_bench(q, W, a.serve_requests)

@@ -62,12 +62,12 @@ struct Prec;
 template <>
 struct Prec<float> {
   static constexpr int kSwz = 5;   // 32 complex64 = 256 B per swizzle group
-  using V = float2;
+  typedef float V __attribute__((ext_vector_type(2)));
 };
 template <>
 struct Prec<double> {
   static constexpr int kSwz = 4;   // 16 complex128 = 256 B per swizzle group
-  using V = double2;
+  typedef double V __attribute__((ext_vector_type(2)));
 };
 
 template <typename R>
@@ -158,6 +158,45 @@ __device__ __forceinline__ void bfly(cx<R>& a, cx<R>& b, R c, R s) {
   b.im = c * B.im - s * A.re;
 }
 
+// Factored forward mixer: mode 0: (a,b) -> (a - i t b, b - i t a);
+// mode 1: (a,b) -> (b + i t a, a + i t b).  The dropped scalar per qubit is
+// cos(beta) resp. -i sin(beta) (applied once per segment elsewhere).
+template <typename R, int LOGR>
+__device__ __forceinline__ void rx_regs_f(cx<R> (&v)[1 << LOGR], int mask, int mode, R t) {
+#pragma unroll
+  for (int k = 0; k < LOGR; ++k) {
+    if (mask & (1 << k)) {
+      if (mode == 0) {
+#pragma unroll
+        for (int j = 0; j < (1 << LOGR); ++j) {
+          if (!(j & (1 << k))) {
+            cx<R>& a = v[j];
+            cx<R>& b = v[j | (1 << k)];
+            const cx<R> A = a, B = b;
+            a.re = fma(t, B.im, A.re);
+            a.im = fma(-t, B.re, A.im);
+            b.re = fma(t, A.im, B.re);
+            b.im = fma(-t, A.re, B.im);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < (1 << LOGR); ++j) {
+          if (!(j & (1 << k))) {
+            cx<R>& a = v[j];
+            cx<R>& b = v[j | (1 << k)];
+            const cx<R> A = a, B = b;
+            a.re = fma(-t, A.im, B.re);
+            a.im = fma(t, A.re, B.im);
+            b.re = fma(-t, B.im, A.re);
+            b.im = fma(t, B.re, A.im);
+          }
+        }
+      }
+    }
+  }
+}
+
 template <typename R, int LOGR>
 __device__ __forceinline__ void rx_regs(cx<R> (&v)[1 << LOGR], int mask, R c, R s) {
 #pragma unroll
@@ -190,91 +229,6 @@ __device__ __forceinline__ cx<float> expmi<float>(double th) {
   return {c, -s};
 }
 
-struct SiteVals {
-  double cz0;
-  double d[kMaxLogR];
-};
-
-// C(z0) and, for each register bit k, the cut change when only vertex q_k
-// flips from 0 to 1 (edges to other register vertices excluded).
-template <int LOGR>
-__device__ SiteVals site_values(const QCONST GraphDev* __restrict__ g, const SiteDesc& S, uint64_t z0) {
-  SiteVals r;
-  const int n = g->n;
-  if (!g->weighted) {
-    int c = 0;
-    for (int v = 0; v < n; ++v) {
-      const uint64_t bI = 0ull - ((z0 >> v) & 1ull);      // b_I of Algorithm 3
-      c += (int)__popcll(g->upper[v] & (bI ^ z0));
-    }
-    r.cz0 = (double)c;
-#pragma unroll
-    for (int k = 0; k < LOGR; ++k) {
-      const uint64_t ax = g->adj[S.q[k]] & ~S.qmask;
-      // __popcll is unsigned: form the signed difference explicitly
-      r.d[k] = (double)((int)__popcll(ax) - 2 * (int)__popcll(ax & z0));
-    }
-  } else {
-    double c = 0.0;
-    const int m = g->m;
-    const QCONST int32_t* eu = cmem<int32_t>(g->eu);
-    const QCONST int32_t* ev = cmem<int32_t>(g->ev);
-    const QCONST double* ew = cmem<double>(g->ew);
-    for (int e = 0; e < m; ++e)
-      if (((z0 >> eu[e]) ^ (z0 >> ev[e])) & 1ull) c += ew[e];
-    r.cz0 = c;
-#pragma unroll
-    for (int k = 0; k < LOGR; ++k) {
-      const int q = S.q[k];
-      double d = 0.0;
-      const QCONST int32_t* nbr = cmem<int32_t>(g->nbr);
-      const QCONST double* nw = cmem<double>(g->nw);
-      for (int i = g->off[q]; i < g->off[q + 1]; ++i) {
-        const int v = nbr[i];
-        if (!((S.qmask >> v) & 1ull)) d += ((z0 >> v) & 1ull) ? -nw[i] : nw[i];
-      }
-      r.d[k] = d;
-    }
-  }
-#pragma unroll
-  for (int k = LOGR; k < kMaxLogR; ++k) r.d[k] = 0.0;
-  return r;
-}
-
-// v[J] *= exp(-i gamma C(z0 ^ J)), or its conjugate when `undo`.  The
-// per-amplitude phase is exp(-i gamma C(z0)) * prod_{k in J} exp(-i gamma d_k)
-// * exp(-i gamma RT[J]); the product over J is split into a low and a high
-// half-tree so only 2^3 + 2^(LOGR-3) partial products stay in registers.
-template <typename R, int LOGR>
-__device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVals& sv, double gamma,
-                                            const QCONST cx<R>* __restrict__ rtph, bool undo) {
-  constexpr int LO = LOGR < 3 ? LOGR : 3;
-  constexpr int HI = LOGR - LO;
-  const double gs = undo ? -gamma : gamma;
-  cx<R> plo[1 << LO], phi[1 << HI];
-  plo[0] = expmi<R>(gs * sv.cz0);
-#pragma unroll
-  for (int k = 0; k < LO; ++k) {
-    const cx<R> e = expmi<R>(gs * sv.d[k]);
-#pragma unroll
-    for (int j = 0; j < (1 << k); ++j) plo[j | (1 << k)] = cmul(plo[j], e);
-  }
-  phi[0] = {(R)1, (R)0};
-#pragma unroll
-  for (int k = 0; k < HI; ++k) {
-    const cx<R> e = expmi<R>(gs * sv.d[LO + k]);
-#pragma unroll
-    for (int j = 0; j < (1 << k); ++j) phi[j | (1 << k)] = cmul(phi[j], e);
-  }
-#pragma unroll
-  for (int j = 0; j < (1 << LOGR); ++j) {
-    const cx<R> rt = rtph[j];
-    const cx<R> t = undo ? cmulc(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt)
-                         : cmul(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt);
-    v[j] = cmul(v[j], t);
-  }
-}
-
 // Sum over the 64-lane wave, then across waves; result valid on thread 0.
 __device__ __forceinline__ void block_reduce2(double& a, double& b, double* red, int nthreads) {
   const int wsz = nthreads < 64 ? nthreads : 64;
@@ -299,6 +253,95 @@ __device__ __forceinline__ void block_reduce2(double& a, double& b, double* red,
   __syncthreads();
 }
 
+struct SiteVals {
+  double cz0;
+  double d[kMaxLogR];
+};
+
+// Per-tile part of the cut decomposition, shared through LDS: C(zbase) and,
+// for each tile bit i, dout_i = sum over out-of-tile neighbours v of the
+// tile vertex u_i of w_uv (1 - 2 zbase_v).
+struct TileCut {
+  double cb;
+  double dout[16];
+};
+
+__device__ void tile_cut(const QCONST GraphDev* __restrict__ g, uint64_t zbase, int K, int L, int h,
+                         uint32_t tid, int nthreads, TileCut* tc, double* red) {
+  const QCONST int32_t* eu = cmem<int32_t>(g->eu);
+  const QCONST int32_t* ev = cmem<int32_t>(g->ev);
+  const QCONST double* ew = cmem<double>(g->ew);
+  double part = 0.0, zero = 0.0;
+  for (int e = tid; e < g->m; e += nthreads)
+    if (((zbase >> eu[e]) ^ (zbase >> ev[e])) & 1ull) part += ew[e];
+  const uint64_t tmask = ((1ull << L) - 1ull) | (((1ull << (K - L)) - 1ull) << h);
+  const QCONST int32_t* nbr = cmem<int32_t>(g->nbr);
+  const QCONST double* nw = cmem<double>(g->nw);
+  for (int i = tid; i < K; i += nthreads) {
+    const int u = i < L ? i : h + (i - L);
+    double d = 0.0;
+    for (int k = g->off[u]; k < g->off[u + 1]; ++k) {
+      const int v = nbr[k];
+      if (!((tmask >> v) & 1ull)) d += ((zbase >> v) & 1ull) ? -nw[k] : nw[k];
+    }
+    tc->dout[i] = d;
+  }
+  block_reduce2(part, zero, red, nthreads);
+  if (tid == 0) tc->cb = part;
+  __syncthreads();
+}
+
+template <int LOGR>
+__device__ __forceinline__ SiteVals site_values(const QCONST double* __restrict__ dtab, const SiteDesc& S,
+                                                const TileCut* tc, uint32_t tb, int b, int K, uint32_t tid,
+                                                int nthreads) {
+  SiteVals r;
+  double c = tc->cb;
+  for (int i = 0; i < K; ++i)
+    if ((tb >> i) & 1u) c += tc->dout[i];
+  r.cz0 = c + dtab[S.f_off + tid];
+#pragma unroll
+  for (int k = 0; k < LOGR; ++k) r.d[k] = tc->dout[b + k] + dtab[S.g_off + k * nthreads + tid];
+#pragma unroll
+  for (int k = LOGR; k < kMaxLogR; ++k) r.d[k] = 0.0;
+  return r;
+}
+
+// v[J] *= exp(-i gamma C(z0 ^ J)), or its conjugate when `undo`.  The
+// per-amplitude phase is exp(-i gamma C(z0)) * prod_{k in J} exp(-i gamma d_k)
+// * exp(-i gamma RT[J]); the product over J is split into a low and a high
+// half-tree so only 2^3 + 2^(LOGR-3) partial products stay in registers.
+template <typename R, int LOGR>
+__device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVals& sv, double gamma,
+                                            const QCONST cx<R>* __restrict__ rtph, bool undo,
+                                            cx<R> pre = {(R)1, (R)0}) {
+  constexpr int LO = LOGR < 3 ? LOGR : 3;
+  constexpr int HI = LOGR - LO;
+  const double gs = undo ? -gamma : gamma;
+  cx<R> plo[1 << LO], phi[1 << HI];
+  plo[0] = cmul(expmi<R>(gs * sv.cz0), pre);
+#pragma unroll
+  for (int k = 0; k < LO; ++k) {
+    const cx<R> e = expmi<R>(gs * sv.d[k]);
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) plo[j | (1 << k)] = cmul(plo[j], e);
+  }
+  phi[0] = {(R)1, (R)0};
+#pragma unroll
+  for (int k = 0; k < HI; ++k) {
+    const cx<R> e = expmi<R>(gs * sv.d[LO + k]);
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) phi[j | (1 << k)] = cmul(phi[j], e);
+  }
+#pragma unroll
+  for (int j = 0; j < (1 << LOGR); ++j) {
+    const cx<R> rt = rtph[j];
+    const cx<R> t = undo ? cmulc(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt)
+                         : cmul(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt);
+    v[j] = cmul(v[j], t);
+  }
+}
+
 __device__ __forceinline__ int find_desc(const PassDesc* __restrict__ descs, int ndesc, int64_t wg) {
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
@@ -307,6 +350,15 @@ __device__ __forceinline__ int find_desc(const PassDesc* __restrict__ descs, int
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Tile handled by this workgroup.  Workgroups are dealt round-robin to the
+// eight XCDs; for a single-descriptor launch, give each XCD a contiguous run
+// of tiles so its L2 and the HBM pages it opens see neighbouring addresses.
+__device__ __forceinline__ int64_t tile_of_block(const PassDesc& D, int ndesc) {
+  const int64_t wg = blockIdx.x;
+  if (ndesc == 1 && (gridDim.x & 7u) == 0) return (wg & 7) * (int64_t)(gridDim.x >> 3) + (wg >> 3);
+  return wg - D.tile_begin;
 }
 
 __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
@@ -320,11 +372,11 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   constexpr int NR = 1 << LOGR;
   __shared__ cx<R> lds[1 << KB];
   __shared__ double red[2 * (kMaxThreads / 64)];
+  __shared__ TileCut tc;
   const uint32_t tid = threadIdx.x;
-  const int64_t wg = blockIdx.x;
-  const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, wg) : 0];
-  const int64_t g = wg - D.tile_begin;
-  const int L = D.L, h = D.h, nr = D.nrounds;
+  const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
+  const int64_t g = tile_of_block(D, ndesc);
+  const int L = D.L, h = D.h, nr = D.nrounds, nth = blockDim.x;
   const uint64_t zbase = tile_zbase(D, g);
   QGLOBAL cx<R>* __restrict__ psi = gmem<cx<R>>(D.psi);
   const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
@@ -342,34 +394,37 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   }
 
   SiteVals sv0{}, sv1{};
-  if (D.flags & PF_SITE0) sv0 = site_values<LOGR>(gr, D.site[0], zt0);
-  if (D.flags & PF_SITE1)
-    sv1 = site_values<LOGR>(gr, D.site[1], zbase | tmem(tbase<LOGR>(tid, D.rb[nr - 1]), L, h));
+  if (D.flags & (PF_SITE0 | PF_SITE1)) {
+    const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
+    tile_cut(gr, zbase, D.K, L, h, tid, nth, &tc, red);
+    if (D.flags & PF_SITE0)
+      sv0 = site_values<LOGR>(dtab, D.site[0], &tc, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
+    if (D.flags & PF_SITE1)
+      sv1 = site_values<LOGR>(dtab, D.site[1], &tc, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
+  }
 
   int cur = 0;
   for (int s = 0; s < D.nseg; ++s) {
     const SegDesc sg = segs[s];
-    if (sg.has_phase) apply_phase<R, LOGR>(v, (s & 1) ? sv1 : sv0, sg.gamma, ctab + sg.ph_off, false);
-    const R c = (R)sg.cb, sn = (R)sg.sb;
-    if (!(s & 1)) {
-      for (int i = 0; i < nr; ++i) {
-        if (i != cur) {
-          transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[i]);
-          cur = i;
-        }
-        rx_regs<R, LOGR>(v, D.rxmask[i], c, sn);
+    if (sg.has_phase)
+      apply_phase<R, LOGR>(v, (s & 1) ? sv1 : sv0, sg.gamma, ctab + sg.ph_off, false,
+                           cx<R>{(R)sg.pre_re, (R)sg.pre_im});
+    const R t = (R)sg.coef;
+    for (int u = 0; u < nr; ++u) {
+      const int i = (s & 1) ? nr - 1 - u : u;
+      if (i != cur) {
+        transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[i]);
+        cur = i;
       }
-    } else {
-      for (int i = nr - 1; i >= 0; --i) {
-        if (i != cur) {
-          transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[i]);
-          cur = i;
-        }
-        rx_regs<R, LOGR>(v, D.rxmask[i], c, sn);
-      }
+      rx_regs_f<R, LOGR>(v, D.rxmask[i], sg.mode, t);
     }
   }
   if (cur != 0) transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[0]);
+  if (D.flags & PF_SCALE) {
+    const cx<R> fs = {(R)D.fscale_re, (R)D.fscale_im};
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = cmul(v[j], fs);
+  }
 
   if (D.flags & PF_EXPECT) {
     // Gray-code walk over the register index: one FP64 add per amplitude.
@@ -430,11 +485,11 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   constexpr int NR = 1 << LOGR;
   __shared__ cx<R> lds[1 << KB];
   __shared__ double red[2 * (kMaxThreads / 64)];
+  __shared__ TileCut tc;
   const uint32_t tid = threadIdx.x;
-  const int64_t wg = blockIdx.x;
-  const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, wg) : 0];
-  const int64_t g = wg - D.tile_begin;
-  const int L = D.L, h = D.h, nr = D.nrounds, nseg = D.nseg;
+  const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
+  const int64_t g = tile_of_block(D, ndesc);
+  const int L = D.L, h = D.h, nr = D.nrounds, nseg = D.nseg, nth = blockDim.x;
   const int64_t nt = D.ntiles;
   const uint64_t zbase = tile_zbase(D, g);
   QGLOBAL cx<R>* __restrict__ phi = gmem<cx<R>>(D.psi);
@@ -450,9 +505,14 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   load_tile<R, LOGR>(l, lamp, zt0, D.rb[0], L, h);
 
   SiteVals sv0{}, sv1{};
-  if (D.flags & PF_SITE0) sv0 = site_values<LOGR>(gr, D.site[0], zt0);
-  if (D.flags & PF_SITE1)
-    sv1 = site_values<LOGR>(gr, D.site[1], zbase | tmem(tbase<LOGR>(tid, D.rb[nr - 1]), L, h));
+  if (D.flags & (PF_SITE0 | PF_SITE1)) {
+    const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
+    tile_cut(gr, zbase, D.K, L, h, tid, nth, &tc, red);
+    if (D.flags & PF_SITE0)
+      sv0 = site_values<LOGR>(dtab, D.site[0], &tc, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
+    if (D.flags & PF_SITE1)
+      sv1 = site_values<LOGR>(dtab, D.site[1], &tc, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
+  }
 
   int cur = 0;
   if ((nseg & 1) && nr > 1) {
@@ -529,7 +589,16 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceJob* __restrict__ jo
   for (int k = J.span_begin; k < J.span_end; ++k) {
     const Span sp = spans[k];
     const QGLOBAL double* p = (const QGLOBAL double*)sp.ptr;
-    for (int64_t i = threadIdx.x; i < sp.count; i += 256) nadd(s, c, p[i]);
+    int64_t i = threadIdx.x;
+    // eight independent loads in flight, then added in index order
+    for (; i + 7 * 256 < sp.count; i += 8 * 256) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = p[i + u * 256];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) nadd(s, c, x[u]);
+    }
+    for (; i < sp.count; i += 256) nadd(s, c, p[i]);
   }
   ss[threadIdx.x] = s;
   cc[threadIdx.x] = c;
@@ -599,8 +668,17 @@ __global__ void __launch_bounds__(256) k_overlap(const cx<Ra>* __restrict__ a, c
   }
 }
 
+// Streaming copy: each thread moves four 16-byte vectors (all loads issued
+// before the stores), one workgroup per 16 KiB.
 __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s, float4* __restrict__ d, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) d[i] = s[i];
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  float4 x[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (base + u * 256 < n) x[u] = s[base + u * 256];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (base + u * 256 < n) d[base + u * 256] = x[u];
 }
 
 // ---------------------------------------------------------------------------
@@ -669,9 +747,8 @@ hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, 
 }
 
 hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st) {
-  int64_t blocks = (n16 + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) blocks = 1;
+  const int64_t blocks = (n16 + 1023) / 1024;
+  if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src, (float4*)dst, n16);
   return hipGetLastError();
 }

@@ -21,6 +21,7 @@ enum : int32_t {
   PF_NO_STORE = 8,    // backward: state is not written back (undoing the first pass)
   PF_SITE0 = 16,      // per-thread cut values needed at the round-0 mapping
   PF_SITE1 = 32,      // ... and at the last round's mapping
+  PF_SCALE = 64,      // multiply by fscale after the last segment
 };
 
 constexpr int kMaxLogR = 5;
@@ -42,20 +43,39 @@ struct GraphDev {
 };
 
 // Where the cost phase / cut value is evaluated: the register mapping of one
-// round.  q[k] is the memory bit (vertex) carried by register bit k.
+// round.  A thread's amplitudes there have indices z0 ^ J, with z0 the
+// thread's index with its register bits clear and J over the register bits;
+// C(z0 ^ J) = C(z0) + sum_{k in J} d_k + RT[J].  Per thread, with S the tile
+// vertices set in the thread's part of the tile index, P all tile vertices
+// that are not register vertices, and dout_u the cut change of flipping tile
+// vertex u alone against the out-of-tile vertices (from the tile's base):
+//   C(z0) = C(zbase) + sum_{u in S} dout_u + F[tid],  F = w(S, tile \ S)
+//   d_k   = dout_{q_k} + G[k][tid],  G = sum_{v in P} w_{q_k v} (1 - 2 [v in S])
+// C(zbase) and dout are computed once per tile; F, G, RT are host tables.
 struct SiteDesc {
-  uint64_t qmask;
-  int32_t q[kMaxLogR];
-  int32_t rt_off;           // offset (doubles) into dtab of the 2^LOGR internal-cut values
+  int32_t q[kMaxLogR];      // memory bit (vertex) of register bit k
+  int32_t rt_off;           // offsets (doubles) into dtab: RT[2^LOGR],
+  int32_t f_off;            //   F[nthreads],
+  int32_t g_off;            //   G[LOGR][nthreads]
 };
 
 // One segment = optional cost phase exp(-i gamma C) then the mixer on the
 // pass's qubit set.  Segments alternate their round order.
+// The forward sweep applies exp(-i beta X) = cos(beta) (I - i tan(beta) X)
+// (mode 0, |cos| >= |sin|) or -i sin(beta) (X + i cot(beta) I) (mode 1) per
+// qubit: 4 FMAs per amplitude pair, with the product sigma of the factored
+// scalars over the pass's qubits applied once per segment -- folded into the
+// next segment's per-thread phase (pre) or, after the last segment, into
+// PassDesc::fscale.  The adjoint sweep uses the unitary form (cb, sb).
 struct SegDesc {
   double gamma, beta;
   double cb, sb;            // cos(beta), sin(beta) in FP64
+  double coef;              // tan(beta) (mode 0) or cot(beta) (mode 1)
+  double pre_re, pre_im;    // sigma of the previous segment of this pass (forward only)
+  int32_t mode;
   int32_t has_phase;
   int32_t ph_off;           // offset (complex elements) into ctab of exp(-i gamma RT[J])
+  int32_t pad;
 };
 
 struct PassDesc {
@@ -76,6 +96,7 @@ struct PassDesc {
   int32_t nseg;
   SiteDesc site[2];         // site 0: mapping of round 0; site 1: of the last round
   double amp0;              // 2^(-n/2)
+  double fscale_re, fscale_im;  // pending mixer scalars, applied at the end when PF_SCALE
 };
 
 // One output value: *out = scale * (sum of the listed spans, in order).

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <complex>
 #include <numeric>
 
@@ -194,11 +195,19 @@ std::vector<SetGeom> make_sets(int n, const PrecCfg& pc) {
 // reverse order when l is odd, so the last set of one layer is the first of
 // the next and both land in one pass (the cost phase of the next layer,
 // diagonal, sits between the two mixer segments inside the tile).
+//
+// The first and last sets of the order carry two mixer segments and a cost
+// phase in their (merged) passes, the others one segment.  With three or
+// more sets the low set -- the largest -- goes second, so it is never a
+// merged pass.
 std::vector<PassSpec> make_schedule(int nsets, int p) {
+  std::vector<int> order(nsets);
+  for (int j = 0; j < nsets; ++j) order[j] = j;
+  if (nsets >= 3) std::swap(order[0], order[1]);
   std::vector<PassSpec> passes;
   for (int l = 0; l < p; ++l) {
     for (int j = 0; j < nsets; ++j) {
-      const int s = (l % 2 == 0) ? j : nsets - 1 - j;
+      const int s = (l % 2 == 0) ? order[j] : order[nsets - 1 - j];
       if (!passes.empty() && passes.back().set == s) {
         passes.back().seg_layer.push_back(l);
         passes.back().seg_phase.push_back(j == 0);
@@ -213,7 +222,7 @@ std::vector<PassSpec> make_schedule(int nsets, int p) {
   }
   if (passes.empty()) {
     PassSpec ps;
-    ps.set = 0;
+    ps.set = order[0];
     passes.push_back(ps);
   }
   passes.front().gen = true;
@@ -224,27 +233,55 @@ std::vector<PassSpec> make_schedule(int nsets, int p) {
 // Memory bit carried by tile bit t.
 static int tile_to_mem(const SetGeom& s, int t) { return t < s.L ? t : s.h + (t - s.L); }
 
+// Host tables of one round mapping (see SiteDesc): RT over the register
+// vertices, and per thread F and G over the thread's set tile vertices.
 static SiteDesc make_site(const SetGeom& s, int round, int logr, const HostGraph& hg, std::vector<double>& dtab) {
   SiteDesc sd;
   memset(&sd, 0, sizeof sd);
   const int b = s.rb[round];
-  int pos[64];
-  for (int v = 0; v < 64; ++v) pos[v] = -1;
-  for (int k = 0; k < logr; ++k) {
-    sd.q[k] = tile_to_mem(s, b + k);
-    sd.qmask |= 1ull << sd.q[k];
-    pos[sd.q[k]] = k;
-  }
-  sd.rt_off = (int32_t)dtab.size();
+  const int K = s.K;
+  const int nth = 1 << (K - logr);
+  int tpos[64];                 // tile bit of each vertex, -1 outside the tile
+  for (int v = 0; v < 64; ++v) tpos[v] = -1;
+  for (int i = 0; i < K; ++i) tpos[tile_to_mem(s, i)] = i;
+  for (int k = 0; k < logr; ++k) sd.q[k] = tile_to_mem(s, b + k);
   const int NR = 1 << logr;
+  sd.rt_off = (int32_t)dtab.size();
   std::vector<double> rt(NR, 0.0);
   for (int e = 0; e < hg.m(); ++e) {
-    const int ku = pos[hg.eu[e]], kv = pos[hg.ev[e]];
-    if (ku < 0 || kv < 0) continue;
+    const int iu = tpos[hg.eu[e]], iv = tpos[hg.ev[e]];
+    if (iu < b || iu >= b + logr || iv < b || iv >= b + logr) continue;
+    const int ku = iu - b, kv = iv - b;
     for (int J = 0; J < NR; ++J)
       if (((J >> ku) ^ (J >> kv)) & 1) rt[J] += hg.weight(e);
   }
   dtab.insert(dtab.end(), rt.begin(), rt.end());
+  // in-tile edges only
+  std::vector<int> ti, tj;
+  std::vector<double> tw;
+  for (int e = 0; e < hg.m(); ++e) {
+    const int iu = tpos[hg.eu[e]], iv = tpos[hg.ev[e]];
+    if (iu < 0 || iv < 0) continue;
+    ti.push_back(iu);
+    tj.push_back(iv);
+    tw.push_back(hg.weight(e));
+  }
+  const uint32_t regmask = ((1u << logr) - 1u) << b;
+  std::vector<double> F(nth, 0.0), G((size_t)logr * nth, 0.0);
+  for (int tid = 0; tid < nth; ++tid) {
+    const uint32_t tb = (tid & ((1u << b) - 1u)) | ((uint32_t)(tid >> b) << (b + logr));
+    for (size_t e = 0; e < ti.size(); ++e) {
+      const int su = (tb >> ti[e]) & 1, sv = (tb >> tj[e]) & 1;
+      if (su != sv) F[tid] += tw[e];
+      const bool ru = (regmask >> ti[e]) & 1u, rv = (regmask >> tj[e]) & 1u;
+      if (ru && !rv) G[(size_t)(ti[e] - b) * nth + tid] += sv ? -tw[e] : tw[e];
+      if (rv && !ru) G[(size_t)(tj[e] - b) * nth + tid] += su ? -tw[e] : tw[e];
+    }
+  }
+  sd.f_off = (int32_t)dtab.size();
+  dtab.insert(dtab.end(), F.begin(), F.end());
+  sd.g_off = (int32_t)dtab.size();
+  dtab.insert(dtab.end(), G.begin(), G.end());
   return sd;
 }
 
@@ -261,6 +298,15 @@ void build_run(const RunRequest& rq, RunImage* img) {
   const int NR = 1 << logr;
 
   *img = RunImage();
+  // site tables depend only on (set, round): build each once
+  std::vector<std::array<SiteDesc, 2>> sites(sets.size());
+  for (size_t k = 0; k < sets.size(); ++k) {
+    sites[k][0] = make_site(sets[k], 0, logr, hg, img->dtab);
+    sites[k][1] = sets[k].nr > 1 ? make_site(sets[k], sets[k].nr - 1, logr, hg, img->dtab) : sites[k][0];
+  }
+  // Mixer scalars still to be applied; folded into the next cost phase, or
+  // applied at the end of the last pass.
+  std::complex<double> pending(1.0, 0.0);
   int64_t part = 0;
   std::vector<int64_t> bwd_part(sched.size(), 0);
   int64_t fwd_part = 0;
@@ -282,11 +328,13 @@ void build_run(const RunRequest& rq, RunImage* img) {
     d.ntiles = ntiles;
     d.nseg = (int)ps.seg_layer.size();
     d.amp0 = pow(2.0, -0.5 * n);
-    d.site[0] = make_site(s, 0, logr, hg, img->dtab);
-    d.site[1] = (s.nr > 1) ? make_site(s, s.nr - 1, logr, hg, img->dtab) : d.site[0];
+    d.site[0] = sites[ps.set][0];
+    d.site[1] = sites[ps.set][1];
     // segments; seg pointer patched at pack time (stored as index in `segs`)
     const int seg0 = (int)img->segs.size();
     bool ph_even = false, ph_odd = false;
+    int kq = 0;   // mixer qubits of this pass
+    for (int r = 0; r < s.nr; ++r) kq += __builtin_popcount(s.rxmask[r]);
     for (int k = 0; k < d.nseg; ++k) {
       const int l = ps.seg_layer[k];
       SegDesc sg;
@@ -295,7 +343,23 @@ void build_run(const RunRequest& rq, RunImage* img) {
       sg.beta = rq.beta[l];
       sg.cb = cos(rq.beta[l]);
       sg.sb = sin(rq.beta[l]);
+      std::complex<double> sigma;
+      if (fabs(sg.cb) >= fabs(sg.sb)) {
+        sg.mode = 0;
+        sg.coef = sg.sb / sg.cb;
+        sigma = std::pow(std::complex<double>(sg.cb, 0.0), kq);
+      } else {
+        sg.mode = 1;
+        sg.coef = sg.cb / sg.sb;
+        sigma = std::pow(std::complex<double>(0.0, -sg.sb), kq);
+      }
       sg.has_phase = ps.seg_phase[k];
+      if (sg.has_phase) {
+        sg.pre_re = pending.real();
+        sg.pre_im = pending.imag();
+        pending = 1.0;
+      }
+      pending *= sigma;
       if (sg.has_phase) {
         (k & 1 ? ph_odd : ph_even) = true;
         const SiteDesc& site = d.site[k & 1];
@@ -309,6 +373,12 @@ void build_run(const RunRequest& rq, RunImage* img) {
       img->segs.push_back(sg);
     }
     d.segs = (const SegDesc*)(intptr_t)seg0;   // index until packed
+    if (ps.expect && pending != std::complex<double>(1.0, 0.0)) {
+      d.fscale_re = pending.real();
+      d.fscale_im = pending.imag();
+      pending = 1.0;
+      d.flags |= PF_SCALE;
+    }
     int flags = 0;
     if (ps.gen) flags |= PF_GEN;
     if (ps.expect) {
@@ -318,7 +388,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
     int fflags = flags;
     if (ph_even || ps.expect) fflags |= PF_SITE0;
     if (ph_odd) fflags |= PF_SITE1;
-    d.flags = fflags;
+    d.flags |= fflags;
     d.psi = rq.psi;
     d.lam = rq.lam;
     d.g = rq.g;
