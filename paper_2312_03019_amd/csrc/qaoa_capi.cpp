@@ -36,6 +36,7 @@ struct qaoa_ctx {
   size_t state_bytes = 0;
   void* lam = nullptr;
   void* dgraph = nullptr;
+  double* dtcut = nullptr;   // per-tile cut tables of the plan's qubit sets
   char* dev_img = nullptr;
   size_t dev_img_cap = 0;
   double* dev_part = nullptr;
@@ -109,6 +110,8 @@ int ensure_device(qaoa_ctx* c) {
   std::vector<char> img(gb);
   build_dev_graph_image(c->hg, img.data(), c->dgraph);
   HIPCHK(hipMemcpy(c->dgraph, img.data(), gb, hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc((void**)&c->dtcut, tile_cut_doubles(c->hg.n, c->prec) * sizeof(double)));
+  HIPCHK(launch_tile_cuts(c->hg.n, c->prec, (const GraphDev*)c->dgraph, c->dtcut, c->stream));
   if (!c->psi) {
     HIPCHK(hipMalloc(&c->psi, c->state_bytes));
     c->own_psi = true;
@@ -150,7 +153,7 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
   if ((rc = grow_device((void**)&c->dev_out, &c->dev_out_cap, img.nout * sizeof(double), c->stream))) return rc;
   if ((rc = grow_host((void**)&c->host_img, &c->host_img_cap, lay.total, c))) return rc;
   if ((rc = grow_host((void**)&c->host_out, &c->host_out_cap, img.nout * sizeof(double), c))) return rc;
-  pack_run(img, lay, c->prec, c->host_img, c->dev_img, c->dev_part, c->dev_out);
+  pack_run(img, lay, c->prec, c->host_img, c->dev_img, c->dev_part, c->dev_out, c->dtcut);
   HIPCHK(hipMemcpyAsync(c->dev_img, c->host_img, lay.total, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipEventRecord(c->upload_done, c->stream));
   c->upload_pending = true;
@@ -218,6 +221,7 @@ void qaoa_destroy(qaoa_ctx* c) {
   if (c->own_psi && c->psi) (void)hipFree(c->psi);
   if (c->lam) (void)hipFree(c->lam);
   if (c->dgraph) (void)hipFree(c->dgraph);
+  if (c->dtcut) (void)hipFree(c->dtcut);
   if (c->dev_img) (void)hipFree(c->dev_img);
   if (c->dev_part) (void)hipFree(c->dev_part);
   if (c->dev_out) (void)hipFree(c->dev_out);

@@ -258,50 +258,58 @@ struct SiteVals {
   double d[kMaxLogR];
 };
 
-// Per-tile part of the cut decomposition, shared through LDS: C(zbase) and,
-// for each tile bit i, dout_i = sum over out-of-tile neighbours v of the
-// tile vertex u_i of w_uv (1 - 2 zbase_v).
-struct TileCut {
-  double cb;
-  double dout[16];
-};
+// Per-tile part of the cut decomposition: C(zbase) and, for each tile bit i,
+// dout_i = sum over out-of-tile neighbours v of the tile vertex u_i of
+// w_uv (1 - 2 zbase_v).  It depends only on the graph and the tile
+// geometry, so it is tabulated once per qubit set (k_tile_cut) and read by
+// the pass kernels with uniform loads.
+__device__ __forceinline__ uint64_t zbase_of(int64_t g, int K, int L, int h) {
+  const int lowfree = h - L;
+  return (((uint64_t)g & ((1ull << lowfree) - 1ull)) << L) | (((uint64_t)g >> lowfree) << (h + K - L));
+}
 
-__device__ void tile_cut(const QCONST GraphDev* __restrict__ g, uint64_t zbase, int K, int L, int h,
-                         uint32_t tid, int nthreads, TileCut* tc, double* red) {
-  const QCONST int32_t* eu = cmem<int32_t>(g->eu);
-  const QCONST int32_t* ev = cmem<int32_t>(g->ev);
-  const QCONST double* ew = cmem<double>(g->ew);
-  double part = 0.0, zero = 0.0;
-  for (int e = tid; e < g->m; e += nthreads)
-    if (((zbase >> eu[e]) ^ (zbase >> ev[e])) & 1ull) part += ew[e];
+__global__ void __launch_bounds__(256) k_tile_cut(const GraphDev* __restrict__ gp, int K, int L, int h,
+                                                  int64_t ntiles, double* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= ntiles) return;
+  const QCONST GraphDev* g_ = cmem<GraphDev>(gp);
+  const QCONST int32_t* eu = cmem<int32_t>(g_->eu);
+  const QCONST int32_t* ev = cmem<int32_t>(g_->ev);
+  const QCONST double* ew = cmem<double>(g_->ew);
+  const QCONST int32_t* nbr = cmem<int32_t>(g_->nbr);
+  const QCONST double* nw = cmem<double>(g_->nw);
+  const uint64_t zb = zbase_of(g, K, L, h);
+  double cb = 0.0;
+  for (int e = 0; e < g_->m; ++e)
+    if (((zb >> eu[e]) ^ (zb >> ev[e])) & 1ull) cb += ew[e];
   const uint64_t tmask = ((1ull << L) - 1ull) | (((1ull << (K - L)) - 1ull) << h);
-  const QCONST int32_t* nbr = cmem<int32_t>(g->nbr);
-  const QCONST double* nw = cmem<double>(g->nw);
-  for (int i = tid; i < K; i += nthreads) {
-    const int u = i < L ? i : h + (i - L);
+  double* row = out + g * kTileCutStride;
+  row[0] = cb;
+  for (int i = 0; i < kTileCutStride - 1; ++i) {
     double d = 0.0;
-    for (int k = g->off[u]; k < g->off[u + 1]; ++k) {
-      const int v = nbr[k];
-      if (!((tmask >> v) & 1ull)) d += ((zbase >> v) & 1ull) ? -nw[k] : nw[k];
+    if (i < K) {
+      const int u = i < L ? i : h + (i - L);
+      for (int k = g_->off[u]; k < g_->off[u + 1]; ++k) {
+        const int v = nbr[k];
+        if (!((tmask >> v) & 1ull)) d += ((zb >> v) & 1ull) ? -nw[k] : nw[k];
+      }
     }
-    tc->dout[i] = d;
+    row[1 + i] = d;
   }
-  block_reduce2(part, zero, red, nthreads);
-  if (tid == 0) tc->cb = part;
-  __syncthreads();
 }
 
 template <int LOGR>
 __device__ __forceinline__ SiteVals site_values(const QCONST double* __restrict__ dtab, const SiteDesc& S,
-                                                const TileCut* tc, uint32_t tb, int b, int K, uint32_t tid,
-                                                int nthreads) {
+                                                const QCONST double* __restrict__ tcrow, uint32_t tb, int b, int K,
+                                                uint32_t tid, int nthreads) {
   SiteVals r;
-  double c = tc->cb;
-  for (int i = 0; i < K; ++i)
-    if ((tb >> i) & 1u) c += tc->dout[i];
+  double c = tcrow[0];
+#pragma unroll
+  for (int i = 0; i < kTileCutStride - 1; ++i)
+    if (i < K && ((tb >> i) & 1u)) c += tcrow[1 + i];
   r.cz0 = c + dtab[S.f_off + tid];
 #pragma unroll
-  for (int k = 0; k < LOGR; ++k) r.d[k] = tc->dout[b + k] + dtab[S.g_off + k * nthreads + tid];
+  for (int k = 0; k < LOGR; ++k) r.d[k] = tcrow[1 + b + k] + dtab[S.g_off + k * nthreads + tid];
 #pragma unroll
   for (int k = LOGR; k < kMaxLogR; ++k) r.d[k] = 0.0;
   return r;
@@ -362,9 +370,7 @@ __device__ __forceinline__ int64_t tile_of_block(const PassDesc& D, int ndesc) {
 }
 
 __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
-  const int lowfree = D.h - D.L;
-  return (((uint64_t)g & ((1ull << lowfree) - 1ull)) << D.L) |
-         (((uint64_t)g >> lowfree) << (D.h + D.K - D.L));
+  return zbase_of(g, D.K, D.L, D.h);
 }
 
 template <typename R, int LOGR, int KB>
@@ -372,7 +378,6 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   constexpr int NR = 1 << LOGR;
   __shared__ cx<R> lds[1 << KB];
   __shared__ double red[2 * (kMaxThreads / 64)];
-  __shared__ TileCut tc;
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
   const int64_t g = tile_of_block(D, ndesc);
@@ -380,7 +385,6 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   const uint64_t zbase = tile_zbase(D, g);
   QGLOBAL cx<R>* __restrict__ psi = gmem<cx<R>>(D.psi);
   const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
-  const QCONST GraphDev* __restrict__ gr = cmem<GraphDev>(D.g);
   const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
 
   const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
@@ -396,11 +400,11 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   SiteVals sv0{}, sv1{};
   if (D.flags & (PF_SITE0 | PF_SITE1)) {
     const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
-    tile_cut(gr, zbase, D.K, L, h, tid, nth, &tc, red);
+    const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
     if (D.flags & PF_SITE0)
-      sv0 = site_values<LOGR>(dtab, D.site[0], &tc, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
+      sv0 = site_values<LOGR>(dtab, D.site[0], tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
     if (D.flags & PF_SITE1)
-      sv1 = site_values<LOGR>(dtab, D.site[1], &tc, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
+      sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
   }
 
   int cur = 0;
@@ -485,7 +489,6 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   constexpr int NR = 1 << LOGR;
   __shared__ cx<R> lds[1 << KB];
   __shared__ double red[2 * (kMaxThreads / 64)];
-  __shared__ TileCut tc;
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
   const int64_t g = tile_of_block(D, ndesc);
@@ -496,7 +499,6 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   QGLOBAL cx<R>* __restrict__ lamp = gmem<cx<R>>(D.lam);
   QGLOBAL double* __restrict__ part = gmem<double>(D.part);
   const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
-  const QCONST GraphDev* __restrict__ gr = cmem<GraphDev>(D.g);
   const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
 
   const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
@@ -507,11 +509,11 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   SiteVals sv0{}, sv1{};
   if (D.flags & (PF_SITE0 | PF_SITE1)) {
     const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
-    tile_cut(gr, zbase, D.K, L, h, tid, nth, &tc, red);
+    const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
     if (D.flags & PF_SITE0)
-      sv0 = site_values<LOGR>(dtab, D.site[0], &tc, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
+      sv0 = site_values<LOGR>(dtab, D.site[0], tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
     if (D.flags & PF_SITE1)
-      sv1 = site_values<LOGR>(dtab, D.site[1], &tc, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
+      sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
   }
 
   int cur = 0;
@@ -743,6 +745,12 @@ hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, 
     hipLaunchKernelGGL((k_overlap<double, float>), grid, block, 0, st, (const cx<double>*)a, (const cx<float>*)b, N, part);
   else
     hipLaunchKernelGGL((k_overlap<double, double>), grid, block, 0, st, (const cx<double>*)a, (const cx<double>*)b, N, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_cut(const GraphDev* g, int K, int L, int h, int64_t ntiles, double* out, hipStream_t st) {
+  const int64_t blocks = (ntiles + 255) / 256;
+  hipLaunchKernelGGL(k_tile_cut, dim3((unsigned)blocks), dim3(256), 0, st, g, K, L, h, ntiles, out);
   return hipGetLastError();
 }
 

@@ -97,7 +97,11 @@ struct PassDesc {
   SiteDesc site[2];         // site 0: mapping of round 0; site 1: of the last round
   double amp0;              // 2^(-n/2)
   double fscale_re, fscale_im;  // pending mixer scalars, applied at the end when PF_SCALE
+  const double *tcut;       // per tile: C(zbase), dout[0..K) (kTileCutStride doubles each)
 };
+
+// Per-tile cut table row: [C(zbase), dout_0 .. dout_{K-1}, 0...].
+constexpr int kTileCutStride = 16;
 
 // One output value: *out = scale * (sum of the listed spans, in order).
 struct ReduceJob {

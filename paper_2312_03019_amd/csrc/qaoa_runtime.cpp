@@ -392,6 +392,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
     d.psi = rq.psi;
     d.lam = rq.lam;
     d.g = rq.g;
+    d.tcut = (const double*)(intptr_t)((int64_t)ps.set * ntiles * kTileCutStride);   // offset until packed
     if (ps.expect) {
       fwd_part = part;
       d.part = (double*)(intptr_t)part;   // offset until packed
@@ -468,8 +469,29 @@ ImageLayout image_layout(const RunImage& img, int prec) {
   return L;
 }
 
+size_t tile_cut_doubles(int n, int prec) {
+  const PrecCfg pc = prec_cfg(prec);
+  int K, logr;
+  tile_shape(n, pc, &K, &logr);
+  return make_sets(n, pc).size() * ((size_t)1 << (n - K)) * kTileCutStride;
+}
+
+hipError_t launch_tile_cuts(int n, int prec, const GraphDev* g, double* tcut, hipStream_t st) {
+  const PrecCfg pc = prec_cfg(prec);
+  int K, logr;
+  tile_shape(n, pc, &K, &logr);
+  const int64_t ntiles = (int64_t)1 << (n - K);
+  const std::vector<SetGeom> sets = make_sets(n, pc);
+  for (size_t k = 0; k < sets.size(); ++k) {
+    hipError_t e = launch_tile_cut(g, sets[k].K, sets[k].L, sets[k].h, ntiles,
+                                   tcut + (int64_t)k * ntiles * kTileCutStride, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 void pack_run(RunImage& img, const ImageLayout& lay, int prec, void* host_buf, char* dev_region, double* part,
-              double* out) {
+              double* out, const double* tcut) {
   char* h = (char*)host_buf;
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) memcpy(h + off, src, bytes);
@@ -493,6 +515,7 @@ void pack_run(RunImage& img, const ImageLayout& lay, int prec, void* host_buf, c
     d.dtab = (const double*)(dev_region + lay.off_dtab);
     d.ctab = (const void*)(dev_region + lay.off_ctab);
     d.part = part + (intptr_t)d.part;
+    d.tcut = tcut + (intptr_t)d.tcut;
   };
   for (auto& d : img.fwd) patch(d);
   for (auto& d : img.bwd) patch(d);

@@ -106,6 +106,10 @@ ImageLayout image_layout(const RunImage& img, int prec);
 // patches device pointers to point into dev_region, the partial buffer
 // `part` and the output array `out` (nout doubles, device).
 void pack_run(RunImage& img, const ImageLayout& lay, int prec, void* host_buf, char* dev_region,
-              double* part, double* out);
+              double* part, double* out, const double* tcut);
+// Doubles of the per-tile cut tables of all qubit sets of an n-qubit plan.
+size_t tile_cut_doubles(int n, int prec);
+// Fill them (device memory `tcut`) for the graph at device address g.
+hipError_t launch_tile_cuts(int n, int prec, const GraphDev* g, double* tcut, hipStream_t st);
 
 }  // namespace qaoa

@@ -94,7 +94,7 @@ struct SReq {
   // device side (scheduler thread)
   RunImage img;
   ImageLayout lay{};
-  size_t graph_bytes = 0, sz_psi = 0, sz_lam = 0, sz_aux = 0;
+  size_t graph_bytes = 0, sz_psi = 0, sz_lam = 0, sz_aux = 0, tcut_doubles = 0;
   size_t off_psi = 0, off_lam = 0, off_aux = 0;
   bool has_mem = false;
   int slot = -1;
@@ -313,6 +313,7 @@ int qaoa_server::step_once(uint64_t step) {
     char* dimg = aux + align256(r->graph_bytes);
     double* dpart = (double*)(dimg + align256(r->lay.total));
     double* dout = dpart + r->img.part_doubles;
+    double* dtcut = (double*)((char*)dpart + align256((r->img.part_doubles + r->img.nout) * sizeof(double)));
     build_dev_graph_image(r->hg, hstage[par] + hoff, dgraph);
     for (auto& d : r->img.fwd) {
       d.psi = psi;
@@ -324,10 +325,11 @@ int qaoa_server::step_once(uint64_t step) {
       d.lam = lam;
       d.g = (const GraphDev*)dgraph;
     }
-    pack_run(r->img, r->lay, prec, hstage[par] + hoff + align256(r->graph_bytes), dimg, dpart, dout);
+    pack_run(r->img, r->lay, prec, hstage[par] + hoff + align256(r->graph_bytes), dimg, dpart, dout, dtcut);
     if (hipMemcpyAsync(dgraph, hstage[par] + hoff, align256(r->graph_bytes) + r->lay.total, hipMemcpyHostToDevice,
                        stream) != hipSuccess)
       return QAOA_EDEVICE;
+    if (launch_tile_cuts(r->hg.n, prec, (const GraphDev*)dgraph, dtcut, stream) != hipSuccess) return QAOA_EDEVICE;
     hoff += align256(r->graph_bytes) + align256(r->lay.total);
     r->uploaded = true;
   }
@@ -503,8 +505,10 @@ int qaoa_serve_submit(qaoa_server* s, const qaoa_request* q, double arrival_time
   r->graph_bytes = dev_graph_bytes(r->hg);
   r->sz_psi = ((size_t)1 << r->hg.n) * pc.elem;
   r->sz_lam = r->grad ? r->sz_psi : 0;
+  r->tcut_doubles = tile_cut_doubles(r->hg.n, s->prec);
   r->sz_aux = align256(r->graph_bytes) + align256(r->lay.total) +
-              align256((r->img.part_doubles + r->img.nout) * sizeof(double));
+              align256((r->img.part_doubles + r->img.nout) * sizeof(double)) +
+              align256(r->tcut_doubles * sizeof(double));
   r->nf = (int)r->img.fwd.size();
   r->nlaunch = r->nf + (int)r->img.bwd.size();
   int K;
