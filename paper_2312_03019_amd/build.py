@@ -18,7 +18,7 @@ SOURCES = ["qaoa_kernels.hip", "qaoa_runtime.cpp", "qaoa_capi.cpp", "qaoa_serve.
 ARCH = os.environ.get("QAOA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
+         "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument", "-Wno-pass-failed"]
 
 
 def _compile(src: str) -> str:

@@ -174,14 +174,14 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
   const PassDesc* dfwd = (const PassDesc*)(c->dev_img + lay.off_fwd);
   for (size_t i = 0; i < nf; ++i) {
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * i], c->stream));
-    HIPCHK(launch_pass(pc.prec, false, logr, dfwd + i, 1, ntiles, nthreads, c->stream));
+    HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[i].shape, dfwd + i, 1, ntiles, nthreads, c->stream));
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * i + 1], c->stream));
   }
   c->ntimed = c->profiling ? (int)nf : 0;
   c->pass_bytes = img.pass_bytes;
   const PassDesc* dbwd = (const PassDesc*)(c->dev_img + lay.off_bwd);
   for (size_t i = 0; i < img.bwd.size(); ++i)
-    HIPCHK(launch_pass(pc.prec, true, logr, dbwd + i, 1, ntiles, nthreads, c->stream));
+    HIPCHK(launch_pass(pc.prec, true, logr, 0, dbwd + i, 1, ntiles, nthreads, c->stream));
   HIPCHK(launch_reduce((const ReduceJob*)(c->dev_img + lay.off_jobs), (const Span*)(c->dev_img + lay.off_spans),
                        (int)img.jobs.size(), c->stream));
   HIPCHK(hipMemcpyAsync(c->host_out, c->dev_out, img.nout * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -135,10 +135,14 @@ __device__ __forceinline__ void store_tile(const cx<R> (&v)[1 << LOGR], QGLOBAL 
 }
 
 // Move the register contents from round mapping `from` to round mapping `to` through LDS.
+//
+// `flip` (tile-index bits of the `from` round's register bits) marks data held
+// at index t that logically belongs to t ^ flip; it is written to its logical
+// place, so the data arrives in the new mapping un-flipped.
 template <typename R, int LOGR>
 __device__ __forceinline__ void transpose(cx<R>* lds, cx<R> (&v)[1 << LOGR], uint32_t tid,
-                                          int from, int to) {
-  const uint32_t s0 = swz<R>(tbase<LOGR>(tid, from));
+                                          int from, int to, uint32_t flip = 0) {
+  const uint32_t s0 = swz<R>(tbase<LOGR>(tid, from) ^ flip);
 #pragma unroll
   for (int j = 0; j < (1 << LOGR); ++j) lds[s0 ^ swz<R>((uint32_t)j << from)] = v[j];
   __syncthreads();
@@ -158,40 +162,26 @@ __device__ __forceinline__ void bfly(cx<R>& a, cx<R>& b, R c, R s) {
   b.im = c * B.im - s * A.re;
 }
 
-// Factored forward mixer: mode 0: (a,b) -> (a - i t b, b - i t a);
-// mode 1: (a,b) -> (b + i t a, a + i t b).  The dropped scalar per qubit is
-// cos(beta) resp. -i sin(beta) (applied once per segment elsewhere).
+// Factored forward mixer on the register bits of one round: for every bit in
+// mask, (a, b) -> (a - i t b, b - i t a); the other bits get t = 0, an exact
+// identity, so the code has no data-dependent branches.  The dropped scalar
+// per qubit (cos beta, or -i sin beta when the segment uses the shifted
+// angle) is applied once per segment elsewhere.
 template <typename R, int LOGR>
-__device__ __forceinline__ void rx_regs_f(cx<R> (&v)[1 << LOGR], int mask, int mode, R t) {
+__device__ __forceinline__ void rx_round(cx<R> (&v)[1 << LOGR], int mask, R t) {
 #pragma unroll
   for (int k = 0; k < LOGR; ++k) {
-    if (mask & (1 << k)) {
-      if (mode == 0) {
+    const R tk = ((mask >> k) & 1) ? t : (R)0;
 #pragma unroll
-        for (int j = 0; j < (1 << LOGR); ++j) {
-          if (!(j & (1 << k))) {
-            cx<R>& a = v[j];
-            cx<R>& b = v[j | (1 << k)];
-            const cx<R> A = a, B = b;
-            a.re = fma(t, B.im, A.re);
-            a.im = fma(-t, B.re, A.im);
-            b.re = fma(t, A.im, B.re);
-            b.im = fma(-t, A.re, B.im);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < (1 << LOGR); ++j) {
-          if (!(j & (1 << k))) {
-            cx<R>& a = v[j];
-            cx<R>& b = v[j | (1 << k)];
-            const cx<R> A = a, B = b;
-            a.re = fma(-t, A.im, B.re);
-            a.im = fma(t, A.re, B.im);
-            b.re = fma(-t, B.im, A.re);
-            b.im = fma(t, B.re, A.im);
-          }
-        }
+    for (int j = 0; j < (1 << LOGR); ++j) {
+      if (!(j & (1 << k))) {
+        cx<R>& a = v[j];
+        cx<R>& b = v[j | (1 << k)];
+        const cx<R> A = a, B = b;
+        a.re = fma(tk, B.im, A.re);
+        a.im = fma(-tk, B.re, A.im);
+        b.re = fma(tk, A.im, B.re);
+        b.im = fma(-tk, A.re, B.im);
       }
     }
   }
@@ -319,12 +309,27 @@ __device__ __forceinline__ SiteVals site_values(const QCONST double* __restrict_
 // per-amplitude phase is exp(-i gamma C(z0)) * prod_{k in J} exp(-i gamma d_k)
 // * exp(-i gamma RT[J]); the product over J is split into a low and a high
 // half-tree so only 2^3 + 2^(LOGR-3) partial products stay in registers.
+// Site values seen from register slots whose logical register index is
+// J ^ f: C = cz0 + sum_{k in f} d_k + sum_{k in J} (+/-) d_k + RT[J ^ f].
+template <int LOGR>
+__device__ __forceinline__ SiteVals flip_site(const SiteVals& sv, uint32_t f) {
+  SiteVals r = sv;
+#pragma unroll
+  for (int k = 0; k < LOGR; ++k) {
+    const bool fk = (f >> k) & 1u;
+    r.cz0 += fk ? sv.d[k] : 0.0;
+    r.d[k] = fk ? -sv.d[k] : sv.d[k];
+  }
+  return r;
+}
+
 template <typename R, int LOGR>
-__device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVals& sv, double gamma,
+__device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVals& sv0, double gamma,
                                             const QCONST cx<R>* __restrict__ rtph, bool undo,
-                                            cx<R> pre = {(R)1, (R)0}) {
+                                            cx<R> pre = {(R)1, (R)0}, uint32_t f = 0) {
   constexpr int LO = LOGR < 3 ? LOGR : 3;
   constexpr int HI = LOGR - LO;
+  const SiteVals sv = flip_site<LOGR>(sv0, f);
   const double gs = undo ? -gamma : gamma;
   cx<R> plo[1 << LO], phi[1 << HI];
   plo[0] = cmul(expmi<R>(gs * sv.cz0), pre);
@@ -343,7 +348,7 @@ __device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVal
   }
 #pragma unroll
   for (int j = 0; j < (1 << LOGR); ++j) {
-    const cx<R> rt = rtph[j];
+    const cx<R> rt = rtph[j ^ f];
     const cx<R> t = undo ? cmulc(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt)
                          : cmul(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt);
     v[j] = cmul(v[j], t);
@@ -373,83 +378,108 @@ __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
   return zbase_of(g, D.K, D.L, D.h);
 }
 
-template <typename R, int LOGR, int KB>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) k_forward(const PassDesc* __restrict__ descs, int ndesc) {
+// One forward pass over one tile.  Template knobs, each either fixed at
+// compile time or -1 / 0 = read from the descriptor (the generic kernel):
+//   NRC rounds per mixer segment, NSC segments, PHM bit s = segment s starts
+//   with the cost phase, GEN synthesise |+>^n instead of loading, EXP 1 =
+//   accumulate <C> and the norm, 2 = also store lam = C psi.
+// With everything fixed the pass is straight-line code (no register merges).
+template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int EXP>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   constexpr int NR = 1 << LOGR;
   __shared__ cx<R> lds[1 << KB];
   __shared__ double red[2 * (kMaxThreads / 64)];
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
   const int64_t g = tile_of_block(D, ndesc);
-  const int L = D.L, h = D.h, nr = D.nrounds, nth = blockDim.x;
+  const int L = D.L, h = D.h, nth = blockDim.x;
+  const int nr = NRC > 0 ? NRC : D.nrounds;
+  const int nseg = NSC > 0 ? NSC : D.nseg;
+  const int flags = D.flags;
+  const bool gen = GEN >= 0 ? GEN != 0 : (flags & PF_GEN) != 0;
+  const int exp = EXP >= 0 ? EXP : ((flags & PF_EXPECT) ? ((flags & PF_WRITE_LAM) ? 2 : 1) : 0);
+  const bool need0 = PHM >= 0 ? ((PHM & 1) || EXP > 0) : (flags & PF_SITE0) != 0;
+  const bool need1 = PHM >= 0 ? ((PHM & 2) != 0) : (flags & PF_SITE1) != 0;
   const uint64_t zbase = tile_zbase(D, g);
-  QGLOBAL cx<R>* __restrict__ psi = gmem<cx<R>>(D.psi);
   const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
   const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
+  const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
+  const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
 
   const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
   cx<R> v[NR];
-  if (D.flags & PF_GEN) {
+  if (gen) {
     const R a = (R)D.amp0;
 #pragma unroll
     for (int j = 0; j < NR; ++j) v[j] = {a, (R)0};
   } else {
-    load_tile<R, LOGR>(v, psi, zt0, D.rb[0], L, h);
+    load_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, D.rb[0], L, h);
   }
-
   SiteVals sv0{}, sv1{};
-  if (D.flags & (PF_SITE0 | PF_SITE1)) {
-    const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
-    const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
-    if (D.flags & PF_SITE0)
-      sv0 = site_values<LOGR>(dtab, D.site[0], tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
-    if (D.flags & PF_SITE1)
-      sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
-  }
+  if (need0) sv0 = site_values<LOGR>(dtab, D.site[0], tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
+  if (need1)
+    sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
 
   int cur = 0;
-  for (int s = 0; s < D.nseg; ++s) {
+  uint32_t fl = 0;   // pending index flips (tile bits) from shifted-angle segments
+#pragma unroll
+  for (int s = 0; s < (NSC > 0 ? NSC : 64); ++s) {
+    if (NSC <= 0 && s >= nseg) break;
     const SegDesc sg = segs[s];
-    if (sg.has_phase)
+    if (PHM >= 0 ? ((PHM >> s) & 1) : sg.has_phase) {
+      __builtin_amdgcn_sched_barrier(0);
       apply_phase<R, LOGR>(v, (s & 1) ? sv1 : sv0, sg.gamma, ctab + sg.ph_off, false,
-                           cx<R>{(R)sg.pre_re, (R)sg.pre_im});
+                           cx<R>{(R)sg.pre_re, (R)sg.pre_im}, fl >> D.rb[cur]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     const R t = (R)sg.coef;
-    for (int u = 0; u < nr; ++u) {
+    const bool flips = sg.mode != 0;
+#pragma unroll
+    for (int u = 0; u < (NRC > 0 ? NRC : kMaxRounds); ++u) {
+      if (NRC <= 0 && u >= nr) break;
       const int i = (s & 1) ? nr - 1 - u : u;
       if (i != cur) {
-        transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[i]);
+        transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[i], fl);
+        fl = 0;
         cur = i;
       }
-      rx_regs_f<R, LOGR>(v, D.rxmask[i], sg.mode, t);
+      rx_round<R, LOGR>(v, D.rxmask[i], t);
+      __builtin_amdgcn_sched_barrier(0);
+      if (flips) fl ^= (uint32_t)D.rxmask[i] << D.rb[i];
     }
   }
-  if (cur != 0) transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[0]);
-  if (D.flags & PF_SCALE) {
+  if (cur != 0) {
+    transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[0], fl);
+    fl = 0;
+  }
+  const uint32_t f = fl >> D.rb[0];   // remaining flips: round-0 register bits
+  if (flags & PF_SCALE) {
     const cx<R> fs = {(R)D.fscale_re, (R)D.fscale_im};
 #pragma unroll
     for (int j = 0; j < NR; ++j) v[j] = cmul(v[j], fs);
   }
 
-  if (D.flags & PF_EXPECT) {
+  if (exp > 0) {
     // Gray-code walk over the register index: one FP64 add per amplitude.
-    const QCONST double* __restrict__ rt = cmem<double>(D.dtab) + D.site[0].rt_off;
+    const SiteVals sv = flip_site<LOGR>(sv0, f);
+    const QCONST double* __restrict__ rt = dtab + D.site[0].rt_off;
     QGLOBAL cx<R>* __restrict__ lam = gmem<cx<R>>(D.lam) + zt0;
-    const bool wl = (D.flags & PF_WRITE_LAM) != 0;
-    double aE = 0.0, aN = 0.0, c = sv0.cz0;
+    double aE = 0.0, aN = 0.0, c = sv.cz0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       const int J = i ^ (i >> 1);
       if (i > 0) {
         const int k = __builtin_ctz(i);
-        c += ((J >> k) & 1) ? sv0.d[k] : -sv0.d[k];
+        c += ((J >> k) & 1) ? sv.d[k] : -sv.d[k];
       }
-      const double cj = c + rt[J];
+      const double cj = c + rt[J ^ f];
       const double pr = (double)v[J].re * v[J].re + (double)v[J].im * v[J].im;
       aE = fma(pr, cj, aE);
       aN += pr;
-      if (wl) {
+      if (exp == 2) {
         const cx<R> lv = {(R)(cj * v[J].re), (R)(cj * v[J].im)};
-        stg(lam + moff<LOGR>(J, D.rb[0], L, h), lv);
+        stg(lam + moff<LOGR>(J ^ f, D.rb[0], L, h), lv);
       }
     }
     block_reduce2(aE, aN, red, blockDim.x);
@@ -459,7 +489,11 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
       part[D.ntiles + g] = aN;
     }
   }
-  if (!(D.flags & PF_NO_STORE)) store_tile<R, LOGR>(v, psi, zt0, D.rb[0], L, h);
+  if (!(flags & PF_NO_STORE)) {
+    QGLOBAL cx<R>* base = gmem<cx<R>>(D.psi) + zt0;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) stg(base + moff<LOGR>(j ^ f, D.rb[0], L, h), v[j]);
+  }
 }
 
 // Im sum over register pairs of conj(l_a) f_b + conj(l_b) f_a, for the qubits in mask.
@@ -686,38 +720,65 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s, floa
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+template <typename R, int KB, int LOGR>
+static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, dim3 grid, dim3 block, hipStream_t st) {
+  switch (shape) {
+#define QAOA_FWD(NRC, CODE, NSC, PHM, GEN, EXP)                                                              \
+  case NRC * 8 + CODE:                                                                                      \
+    hipLaunchKernelGGL((k_fwd<R, LOGR, KB, NRC, NSC, PHM, GEN, EXP>), grid, block, 0, st, d, ndesc);        \
+    return;
+#define QAOA_FWD_NR(NRC)                                      \
+  QAOA_FWD(NRC, kShapeFirst, 1, 1, 1, 0)                      \
+  QAOA_FWD(NRC, kShapeSingle, 1, 0, 0, 0)                     \
+  QAOA_FWD(NRC, kShapeMerged, 2, 2, 0, 0)                     \
+  QAOA_FWD(NRC, kShapeLast, 1, 0, 0, 1)                       \
+  QAOA_FWD(NRC, kShapeLastLam, 1, 0, 0, 2)
+    QAOA_FWD_NR(1)
+    QAOA_FWD_NR(2)
+    QAOA_FWD_NR(3)
+#undef QAOA_FWD_NR
+#undef QAOA_FWD
+    default:
+      hipLaunchKernelGGL((k_fwd<R, LOGR, KB, 0, 0, -1, -1, -1>), grid, block, 0, st, d, ndesc);
+  }
+}
+
 template <typename R, int KB>
-static hipError_t launch_pass_t(bool backward, int logr, const PassDesc* d, int ndesc, int64_t nblocks,
+static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDesc* d, int ndesc, int64_t nblocks,
                                 int nthreads, hipStream_t st) {
   const dim3 grid((unsigned)nblocks), block((unsigned)nthreads);
-#define QAOA_CASE(LR)                                                                  \
-  case LR:                                                                             \
-    if (backward) hipLaunchKernelGGL((k_backward<R, LR, KB>), grid, block, 0, st, d, ndesc); \
-    else hipLaunchKernelGGL((k_forward<R, LR, KB>), grid, block, 0, st, d, ndesc);   \
-    break;
-  switch (logr) {
-    QAOA_CASE(1)
-    QAOA_CASE(2)
-    QAOA_CASE(3)
-    QAOA_CASE(4)
-    case 5:
-      if constexpr (sizeof(R) == 4) {
-        if (backward) hipLaunchKernelGGL((k_backward<R, 5, KB>), grid, block, 0, st, d, ndesc);
-        else hipLaunchKernelGGL((k_forward<R, 5, KB>), grid, block, 0, st, d, ndesc);
-        break;
-      }
-      return hipErrorInvalidValue;
-    default:
-      return hipErrorInvalidValue;
+  constexpr int LMAX = sizeof(R) == 4 ? kLogRC64 : kLogRC128;
+  if (logr < 1 || logr > LMAX) return hipErrorInvalidValue;
+  if (backward) {
+#define QAOA_BWD(LR) \
+  if (logr == LR) hipLaunchKernelGGL((k_backward<R, LR, KB>), grid, block, 0, st, d, ndesc);
+    QAOA_BWD(1)
+    QAOA_BWD(2)
+    QAOA_BWD(3)
+    QAOA_BWD(4)
+    if constexpr (LMAX >= 5) QAOA_BWD(5)
+#undef QAOA_BWD
+    return hipGetLastError();
   }
-#undef QAOA_CASE
+  if (logr == LMAX) {
+    launch_fwd_shaped<R, KB, LMAX>(shape, d, ndesc, grid, block, st);
+    return hipGetLastError();
+  }
+#define QAOA_GEN(LR) \
+  if (logr == LR) hipLaunchKernelGGL((k_fwd<R, LR, KB, 0, 0, -1, -1, -1>), grid, block, 0, st, d, ndesc);
+  QAOA_GEN(1)
+  QAOA_GEN(2)
+  QAOA_GEN(3)
+  if constexpr (LMAX >= 5) QAOA_GEN(4)
+#undef QAOA_GEN
   return hipGetLastError();
 }
 
-hipError_t launch_pass(int prec, bool backward, int logr, const PassDesc* d, int ndesc, int64_t nblocks,
+hipError_t launch_pass(int prec, bool backward, int logr, int shape, const PassDesc* d, int ndesc, int64_t nblocks,
                        int nthreads, hipStream_t st) {
-  if (prec == 1) return launch_pass_t<float, kTileBitsC64>(backward, logr, d, ndesc, nblocks, nthreads, st);
-  return launch_pass_t<double, kTileBitsC128>(backward, logr, d, ndesc, nblocks, nthreads, st);
+  if (prec == 1)
+    return launch_pass_t<float, kTileBitsC64>(backward, logr, shape, d, ndesc, nblocks, nthreads, st);
+  return launch_pass_t<double, kTileBitsC128>(backward, logr, shape, d, ndesc, nblocks, nthreads, st);
 }
 
 hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hipStream_t st) {

@@ -15,9 +15,20 @@ constexpr int kLogRC128 = 4;    // 16 amplitudes per thread
 constexpr int kPassengerC64 = 4;   // high passes keep >= 16 contiguous complex64 (128 B)
 constexpr int kPassengerC128 = 3;  // ... >= 8 contiguous complex128 (128 B)
 
+// Forward pass shapes with a specialised kernel (at full register width):
+// shape = rounds * 8 + code; 0 selects the generic kernel.
+enum : int {
+  kShapeFirst = 1,     // |+>^n synthesised, cost phase, one mixer segment
+  kShapeSingle = 2,    // one mixer segment
+  kShapeMerged = 3,    // mixer segment, cost phase, mixer segment
+  kShapeLast = 4,      // one mixer segment, then <C> and norm
+  kShapeLastLam = 5,   // ... and lam = C psi
+};
+
 // prec: 1 = complex64, 0 = complex128.  One workgroup per tile; descriptors
-// are found by tile_begin when ndesc > 1.
-hipError_t launch_pass(int prec, bool backward, int logr, const PassDesc* d, int ndesc, int64_t nblocks,
+// are found by tile_begin when ndesc > 1.  All descriptors of one launch
+// share logr and (forward) shape.
+hipError_t launch_pass(int prec, bool backward, int logr, int shape, const PassDesc* d, int ndesc, int64_t nblocks,
                        int nthreads, hipStream_t st);
 hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hipStream_t st);
 hipError_t launch_cut_table(const GraphDev* g, bool weighted, void* out, int64_t N, hipStream_t st);

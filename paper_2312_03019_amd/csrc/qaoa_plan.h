@@ -62,15 +62,17 @@ struct SiteDesc {
 // One segment = optional cost phase exp(-i gamma C) then the mixer on the
 // pass's qubit set.  Segments alternate their round order.
 // The forward sweep applies exp(-i beta X) = cos(beta) (I - i tan(beta) X)
-// (mode 0, |cos| >= |sin|) or -i sin(beta) (X + i cot(beta) I) (mode 1) per
-// qubit: 4 FMAs per amplitude pair, with the product sigma of the factored
-// scalars over the pass's qubits applied once per segment -- folded into the
-// next segment's per-thread phase (pre) or, after the last segment, into
-// PassDesc::fscale.  The adjoint sweep uses the unitary form (cb, sb).
+// (mode 0, |cos| >= |sin|) or, with b' = beta - pi/2,
+// (-i sin(beta)) X (I - i tan(b') X) (mode 1): always 4 FMAs per amplitude
+// pair with |t| <= 1.  Mode 1's X on each mixer qubit is an index flip the
+// kernel tracks and absorbs into LDS/HBM addresses.  The product sigma of the
+// factored scalars is carried on the host and folded into the next cost
+// phase (pre) or applied after the last pass (PassDesc::fscale).  The adjoint
+// sweep uses the unitary form (cb, sb).
 struct SegDesc {
   double gamma, beta;
   double cb, sb;            // cos(beta), sin(beta) in FP64
-  double coef;              // tan(beta) (mode 0) or cot(beta) (mode 1)
+  double coef;              // tan(beta) (mode 0) or tan(beta - pi/2) = -cot(beta) (mode 1)
   double pre_re, pre_im;    // sigma of the previous segment of this pass (forward only)
   int32_t mode;
   int32_t has_phase;
@@ -94,6 +96,8 @@ struct PassDesc {
   int32_t rxmask[kMaxRounds];  // which register bits get the mixer in that round
   int32_t flags;
   int32_t nseg;
+  int32_t shape;            // forward kernel specialisation (see launch_pass)
+  int32_t pad_;
   SiteDesc site[2];         // site 0: mapping of round 0; site 1: of the last round
   double amp0;              // 2^(-n/2)
   double fscale_re, fscale_im;  // pending mixer scalars, applied at the end when PF_SCALE

@@ -285,6 +285,19 @@ static SiteDesc make_site(const SetGeom& s, int round, int logr, const HostGraph
   return sd;
 }
 
+// Which specialised forward kernel runs a pass (0 = the generic one).
+static int forward_shape(const PassDesc& d, bool full_width, const SegDesc* segs) {
+  if (!full_width || d.nrounds < 1 || d.nrounds > 3) return 0;
+  const bool gen = d.flags & PF_GEN, ex = d.flags & PF_EXPECT, lam = d.flags & PF_WRITE_LAM;
+  const bool ph0 = d.nseg >= 1 && segs[0].has_phase, ph1 = d.nseg >= 2 && segs[1].has_phase;
+  int code = 0;
+  if (d.nseg == 1 && gen && ph0 && !ex) code = kShapeFirst;
+  else if (d.nseg == 1 && !gen && !ph0 && !ex) code = kShapeSingle;
+  else if (d.nseg == 2 && !gen && !ph0 && ph1 && !ex) code = kShapeMerged;
+  else if (d.nseg == 1 && !gen && !ph0 && ex) code = lam ? kShapeLastLam : kShapeLast;
+  return code ? d.nrounds * 8 + code : 0;
+}
+
 void build_run(const RunRequest& rq, RunImage* img) {
   const HostGraph& hg = *rq.hg;
   const int n = hg.n;
@@ -349,8 +362,10 @@ void build_run(const RunRequest& rq, RunImage* img) {
         sg.coef = sg.sb / sg.cb;
         sigma = std::pow(std::complex<double>(sg.cb, 0.0), kq);
       } else {
+        // exp(-i b X) = (-i X) exp(-i (b - pi/2) X): factored with t = tan(b - pi/2)
+        // = -cot(b); the X on every mixer qubit is tracked as an index flip.
         sg.mode = 1;
-        sg.coef = sg.cb / sg.sb;
+        sg.coef = -sg.cb / sg.sb;
         sigma = std::pow(std::complex<double>(0.0, -sg.sb), kq);
       }
       sg.has_phase = ps.seg_phase[k];
@@ -389,6 +404,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
     if (ph_even || ps.expect) fflags |= PF_SITE0;
     if (ph_odd) fflags |= PF_SITE1;
     d.flags |= fflags;
+    d.shape = forward_shape(d, logr == pc.logr_max, img->segs.data() + seg0);
     d.psi = rq.psi;
     d.lam = rq.lam;
     d.g = rq.g;

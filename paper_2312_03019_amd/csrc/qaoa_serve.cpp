@@ -276,7 +276,7 @@ int qaoa_server::step_once(uint64_t step) {
   for (SReq* r : fresh) hneed += align256(r->graph_bytes) + align256(r->lay.total);
   struct Group {
     bool bwd;
-    int logr, nthreads;
+    int logr, nthreads, shape;
     std::vector<PassDesc> d;
     int64_t tiles;
   };
@@ -286,11 +286,12 @@ int qaoa_server::step_once(uint64_t step) {
     if (r->next >= r->nlaunch) continue;
     const bool bwd = r->next >= r->nf;
     PassDesc d = bwd ? r->img.bwd[r->next - r->nf] : r->img.fwd[r->next];
+    const int shape = bwd ? 0 : d.shape;
     Group* g = nullptr;
     for (auto& x : groups)
-      if (x.bwd == bwd && x.logr == r->logr && x.nthreads == r->nthreads) g = &x;
+      if (x.bwd == bwd && x.logr == r->logr && x.nthreads == r->nthreads && x.shape == shape) g = &x;
     if (!g) {
-      groups.push_back(Group{bwd, r->logr, r->nthreads, {}, 0});
+      groups.push_back(Group{bwd, r->logr, r->nthreads, shape, {}, 0});
       g = &groups.back();
     }
     d.tile_begin = g->tiles;
@@ -340,11 +341,12 @@ int qaoa_server::step_once(uint64_t step) {
     if (r->next >= r->nlaunch) continue;
     const bool bwd = r->next >= r->nf;
     PassDesc d = bwd ? r->img.bwd[r->next - r->nf] : r->img.fwd[r->next];
+    const int shape = bwd ? 0 : d.shape;
     Group* g = nullptr;
     for (auto& x : groups)
-      if (x.bwd == bwd && x.logr == r->logr && x.nthreads == r->nthreads) g = &x;
+      if (x.bwd == bwd && x.logr == r->logr && x.nthreads == r->nthreads && x.shape == shape) g = &x;
     if (!g) {
-      groups.push_back(Group{bwd, r->logr, r->nthreads, {}, 0});
+      groups.push_back(Group{bwd, r->logr, r->nthreads, shape, {}, 0});
       g = &groups.back();
     }
     d.tile_begin = g->tiles;
@@ -364,7 +366,7 @@ int qaoa_server::step_once(uint64_t step) {
     return QAOA_EDEVICE;
   for (size_t i = 0; i < groups.size(); ++i) {
     const Group& g = groups[i];
-    if (launch_pass(prec == QAOA_C64 ? 1 : 0, g.bwd, g.logr, (const PassDesc*)(dstage[par] + goff[i]),
+    if (launch_pass(prec == QAOA_C64 ? 1 : 0, g.bwd, g.logr, g.shape, (const PassDesc*)(dstage[par] + goff[i]),
                     (int)g.d.size(), g.tiles, g.nthreads, stream) != hipSuccess)
       return QAOA_EDEVICE;
   }
