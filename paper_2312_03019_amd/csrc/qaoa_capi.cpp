@@ -27,7 +27,6 @@ struct qaoa_ctx {
   HostGraph hg;
   int prec = QAOA_C128;
   int device = 0;
-  int cus = 0;
   bool dev_ready = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -101,7 +100,6 @@ int grow_host(void** p, size_t* cap, size_t need, qaoa_ctx* c) {
 int ensure_device(qaoa_ctx* c) {
   if (c->dev_ready) return QAOA_OK;
   HIPCHK(hipGetDevice(&c->device));
-  HIPCHK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
   if (!c->stream && !c->stream_bound) {
     // default: a private non-blocking stream at default priority
     HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
@@ -174,11 +172,9 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
     }
   }
   const PassDesc* dfwd = (const PassDesc*)(c->dev_img + lay.off_fwd);
-  // forward passes run persistently: two resident workgroups per CU (LDS-bound)
-  const int64_t fwd_blocks = persistent_blocks(ntiles, c->cus);
   for (size_t i = 0; i < nf; ++i) {
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * i], c->stream));
-    HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[i].shape, dfwd + i, 1, fwd_blocks, nthreads, c->stream));
+    HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[i].shape, dfwd + i, 1, ntiles, nthreads, c->stream));
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * i + 1], c->stream));
   }
   c->ntimed = c->profiling ? (int)nf : 0;

@@ -288,45 +288,21 @@ __global__ void __launch_bounds__(256) k_tile_cut(const GraphDev* __restrict__ g
   }
 }
 
-// The tile-independent per-thread part of a site: F[tid], G[k][tid].
-struct SiteTab {
-  double f;
-  double g[kMaxLogR];
-};
-
 template <int LOGR>
-__device__ __forceinline__ SiteTab site_tab(const QCONST double* __restrict__ dtab, const SiteDesc& S, uint32_t tid,
-                                            int nthreads) {
-  SiteTab t;
-  t.f = dtab[S.f_off + tid];
-#pragma unroll
-  for (int k = 0; k < LOGR; ++k) t.g[k] = dtab[S.g_off + k * nthreads + tid];
-#pragma unroll
-  for (int k = LOGR; k < kMaxLogR; ++k) t.g[k] = 0.0;
-  return t;
-}
-
-template <int LOGR>
-__device__ __forceinline__ SiteVals site_values(const SiteTab& T, const QCONST double* __restrict__ tcrow,
-                                                uint32_t tb, int b, int K) {
+__device__ __forceinline__ SiteVals site_values(const QCONST double* __restrict__ dtab, const SiteDesc& S,
+                                                const QCONST double* __restrict__ tcrow, uint32_t tb, int b, int K,
+                                                uint32_t tid, int nthreads) {
   SiteVals r;
   double c = tcrow[0];
 #pragma unroll
   for (int i = 0; i < kTileCutStride - 1; ++i)
     if (i < K && ((tb >> i) & 1u)) c += tcrow[1 + i];
-  r.cz0 = c + T.f;
+  r.cz0 = c + dtab[S.f_off + tid];
 #pragma unroll
-  for (int k = 0; k < LOGR; ++k) r.d[k] = tcrow[1 + b + k] + T.g[k];
+  for (int k = 0; k < LOGR; ++k) r.d[k] = tcrow[1 + b + k] + dtab[S.g_off + k * nthreads + tid];
 #pragma unroll
   for (int k = LOGR; k < kMaxLogR; ++k) r.d[k] = 0.0;
   return r;
-}
-
-template <int LOGR>
-__device__ __forceinline__ SiteVals site_values(const QCONST double* __restrict__ dtab, const SiteDesc& S,
-                                                const QCONST double* __restrict__ tcrow, uint32_t tb, int b, int K,
-                                                uint32_t tid, int nthreads) {
-  return site_values<LOGR>(site_tab<LOGR>(dtab, S, tid, nthreads), tcrow, tb, b, K);
 }
 
 // v[J] *= exp(-i gamma C(z0 ^ J)), or its conjugate when `undo`.  The
@@ -408,27 +384,42 @@ __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
 //   with the cost phase, GEN synthesise |+>^n instead of loading, EXP 1 =
 //   accumulate <C> and the norm, 2 = also store lam = C psi.
 // With everything fixed the pass is straight-line code (no register merges).
-// Everything of a forward pass after the tile is in registers: cost phases,
-// mixer rounds, <C>, store.  T0/T1: per-thread site tables of the pass.
-template <typename R, int LOGR, int NRC, int NSC, int PHM, int GEN, int EXP>
-__device__ __forceinline__ void fwd_tile(const PassDesc& D, cx<R> (&v)[1 << LOGR], int64_t g, uint64_t zt0,
-                                         const SiteTab& T0, const SiteTab& T1, cx<R>* lds, double* red,
-                                         uint32_t tid) {
+template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int EXP>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   constexpr int NR = 1 << LOGR;
-  const int L = D.L, h = D.h;
+  __shared__ cx<R> lds[1 << KB];
+  __shared__ double red[2 * (kMaxThreads / 64)];
+  const uint32_t tid = threadIdx.x;
+  const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
+  const int64_t g = tile_of_block(D, ndesc);
+  const int L = D.L, h = D.h, nth = blockDim.x;
   const int nr = NRC > 0 ? NRC : D.nrounds;
   const int nseg = NSC > 0 ? NSC : D.nseg;
   const int flags = D.flags;
+  const bool gen = GEN >= 0 ? GEN != 0 : (flags & PF_GEN) != 0;
   const int exp = EXP >= 0 ? EXP : ((flags & PF_EXPECT) ? ((flags & PF_WRITE_LAM) ? 2 : 1) : 0);
   const bool need0 = PHM >= 0 ? ((PHM & 1) || EXP > 0) : (flags & PF_SITE0) != 0;
   const bool need1 = PHM >= 0 ? ((PHM & 2) != 0) : (flags & PF_SITE1) != 0;
+  const uint64_t zbase = tile_zbase(D, g);
   const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
   const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
   const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
   const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
+
+  const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
+  cx<R> v[NR];
+  if (gen) {
+    const R a = (R)D.amp0;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = {a, (R)0};
+  } else {
+    load_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, D.rb[0], L, h);
+  }
   SiteVals sv0{}, sv1{};
-  if (need0) sv0 = site_values<LOGR>(T0, tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K);
-  if (need1) sv1 = site_values<LOGR>(T1, tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K);
+  if (need0) sv0 = site_values<LOGR>(dtab, D.site[0], tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
+  if (need1)
+    sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
 
   int cur = 0;
   uint32_t fl = 0;   // pending index flips (tile bits) from shifted-angle segments
@@ -502,81 +493,6 @@ __device__ __forceinline__ void fwd_tile(const PassDesc& D, cx<R> (&v)[1 << LOGR
     QGLOBAL cx<R>* base = gmem<cx<R>>(D.psi) + zt0;
 #pragma unroll
     for (int j = 0; j < NR; ++j) stg(base + moff<LOGR>(j ^ f, D.rb[0], L, h), v[j]);
-  }
-}
-
-// One forward pass.  Template knobs, each either fixed at compile time or
-// -1 / 0 = read from the descriptor (the generic kernel):
-//   NRC rounds per mixer segment, NSC segments, PHM bit s = segment s starts
-//   with the cost phase, GEN synthesise |+>^n instead of loading, EXP 1 =
-//   accumulate <C> and the norm, 2 = also store lam = C psi.
-// With everything fixed the pass is straight-line code (no register merges).
-// A single-descriptor launch with fewer workgroups than tiles runs
-// persistently: each workgroup walks a run of tiles inside one XCD's share
-// and loads the next tile into a second register set while it computes the
-// current one, so HBM reads stay in flight through the compute phases.
-template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int EXP>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
-  constexpr int NR = 1 << LOGR;
-  __shared__ cx<R> lds[1 << KB];
-  __shared__ double red[2 * (kMaxThreads / 64)];
-  const uint32_t tid = threadIdx.x;
-  const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
-  const int nth = blockDim.x;
-  const int flags = D.flags;
-  const bool gen = GEN >= 0 ? GEN != 0 : (flags & PF_GEN) != 0;
-  const bool need0 = PHM >= 0 ? ((PHM & 1) || EXP > 0) : (flags & PF_SITE0) != 0;
-  const bool need1 = PHM >= 0 ? ((PHM & 2) != 0) : (flags & PF_SITE1) != 0;
-  const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
-  SiteTab T0{}, T1{};
-  if (need0) T0 = site_tab<LOGR>(dtab, D.site[0], tid, nth);
-  if (need1) T1 = site_tab<LOGR>(dtab, D.site[1], tid, nth);
-  const uint64_t tt = tmem(tbase<LOGR>(tid, D.rb[0]), D.L, D.h);
-  const QGLOBAL cx<R>* __restrict__ src = gmem<cx<R>>(D.psi);
-  const R a0 = (R)D.amp0;
-  const int64_t T = D.ntiles;
-  const bool persistent = ndesc == 1 && T >= 8 && (int64_t)gridDim.x < T && (gridDim.x & 7u) == 0;
-  // Tile sequence: persistent workgroups walk [base, base + cnt) with stride
-  // per inside one XCD's share (XCD x = blockIdx % 8 owns tiles [x T/8,
-  // (x+1) T/8)); otherwise one tile per workgroup.
-  int64_t base, cnt, per, k;
-  if (persistent) {
-    cnt = T >> 3;
-    base = (int64_t)(blockIdx.x & 7u) * cnt;
-    per = gridDim.x >> 3;
-    k = blockIdx.x >> 3;
-  } else {
-    base = tile_of_block(D, ndesc);
-    cnt = 1;
-    per = 1;
-    k = 0;
-  }
-  if (k >= cnt) return;
-  cx<R> v[NR], nx[NR];
-  if (!gen) load_tile<R, LOGR>(nx, src, tile_zbase(D, base + k) | tt, D.rb[0], D.L, D.h);
-  for (;;) {
-    // Opaque copies of the per-thread index values: keeps the compiler from
-    // hoisting every per-register LDS and HBM address out of the tile loop
-    // (which would pin ~100 VGPRs for the whole kernel).
-    uint32_t tid_l = tid;
-    uint64_t tt_l = tt;
-    asm volatile("" : "+v"(tid_l), "+v"(tt_l));
-    if (gen) {
-#pragma unroll
-      for (int j = 0; j < NR; ++j) v[j] = {a0, (R)0};
-    } else {
-#pragma unroll
-      for (int j = 0; j < NR; ++j) v[j] = nx[j];
-    }
-    const int64_t kn = k + per;
-    __builtin_amdgcn_sched_barrier(0);
-    if (kn < cnt && !gen) load_tile<R, LOGR>(nx, src, tile_zbase(D, base + kn) | tt_l, D.rb[0], D.L, D.h);
-    __builtin_amdgcn_sched_barrier(0);
-    fwd_tile<R, LOGR, NRC, NSC, PHM, GEN, EXP>(D, v, base + k, tile_zbase(D, base + k) | tt_l, T0, T1, lds, red,
-                                               tid_l);
-    if (kn >= cnt) break;
-    k = kn;
   }
 }
 

@@ -54,15 +54,6 @@ struct PrecCfg {
 };
 PrecCfg prec_cfg(int prec);
 
-// Grid of a single-descriptor forward launch: every tile gets a workgroup
-// when that fits in two per CU; otherwise two workgroups per CU (a multiple
-// of 8, the XCD count) walk the tiles persistently.
-inline int64_t persistent_blocks(int64_t ntiles, int cus) {
-  const int64_t cap = 2 * (int64_t)(cus > 0 ? cus : 256);
-  if (ntiles <= cap || ntiles < 8 || cap < 8) return ntiles;
-  return cap & ~(int64_t)7;
-}
-
 // Tile bits and register bits used for an n-qubit state.
 void tile_shape(int n, const PrecCfg& pc, int* K, int* logr);
 std::vector<SetGeom> make_sets(int n, const PrecCfg& pc);
