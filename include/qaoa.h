@@ -88,8 +88,10 @@ int qaoa_expect(qaoa_ctx *ctx, double *expect_out, double *norm_out);
 
 /* <C> and its gradient d<C>/dgamma_l, d<C>/dbeta_l for l < p, by one forward
  * sweep and one adjoint backward sweep on the device (two state vectors).
- * dgamma and dbeta are caller arrays of p doubles.  Leaves the final state
- * psi_p on the device as qaoa_run would. */
+ * dgamma and dbeta are caller arrays of p doubles.  Synchronises the stream.
+ * The backward sweep overwrites the state buffer, so afterwards there is no
+ * state to read: qaoa_get_state / qaoa_fidelity return QAOA_ESTATE until the
+ * next qaoa_run. */
 int qaoa_grad(qaoa_ctx *ctx, int p, const double *gamma, const double *beta,
               double *expect_out, double *dgamma, double *dbeta);
 

@@ -51,6 +51,7 @@ struct qaoa_ctx {
   bool upload_pending = false;
   bool have_state = false;
   bool have_expect = false;
+  bool complemented = false;   // the state buffer holds psi(~z) (reversed order)
   bool profiling = false;
   std::vector<hipEvent_t> ev;
   int ntimed = 0;
@@ -185,6 +186,12 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
   HIPCHK(launch_reduce((const ReduceJob*)(c->dev_img + lay.off_jobs), (const Span*)(c->dev_img + lay.off_spans),
                        (int)img.jobs.size(), c->stream));
   HIPCHK(hipMemcpyAsync(c->host_out, c->dev_out, img.nout * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  c->complemented = img.complemented;
+  // A caller-owned state buffer is left in natural order.
+  if (c->complemented && !c->own_psi && !grad) {
+    HIPCHK(launch_reverse(c->prec == QAOA_C64 ? 1 : 0, c->psi, (int64_t)1 << c->hg.n, c->stream));
+    c->complemented = false;
+  }
   return QAOA_OK;
 }
 
@@ -347,6 +354,16 @@ int qaoa_get_state(qaoa_ctx* c, void* host_out, size_t bytes) {
   }
   HIPCHK(hipMemcpyAsync(host_out, c->psi, bytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->complemented) {   // stored as psi(~z): reverse into natural order
+    const size_t N = (size_t)1 << c->hg.n, el = prec_cfg(c->prec).elem;
+    char* h = (char*)host_out;
+    char tmp[16];
+    for (size_t i = 0; i < N / 2; ++i) {
+      memcpy(tmp, h + i * el, el);
+      memcpy(h + i * el, h + (N - 1 - i) * el, el);
+      memcpy(h + (N - 1 - i) * el, tmp, el);
+    }
+  }
   return QAOA_OK;
 }
 
@@ -392,7 +409,8 @@ int qaoa_fidelity(qaoa_ctx* a, qaoa_ctx* b, double* f_out) {
   double h[4] = {0, 0, 0, 0};
   hipError_t e = hipMemcpy(dj, jobs, sizeof jobs, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ds, spans, sizeof spans, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_overlap(a->prec, a->psi, b->prec, b->psi, N, (double*)d, nb, a->stream);
+  const int rev = a->complemented != b->complemented ? 1 : 0;
+  if (e == hipSuccess) e = launch_overlap(a->prec, a->psi, b->prec, b->psi, N, (double*)d, nb, rev, a->stream);
   if (e == hipSuccess) e = launch_reduce((const ReduceJob*)dj, (const Span*)ds, 4, a->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, a->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(a->stream);

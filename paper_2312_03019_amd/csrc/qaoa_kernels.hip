@@ -135,14 +135,9 @@ __device__ __forceinline__ void store_tile(const cx<R> (&v)[1 << LOGR], QGLOBAL 
 }
 
 // Move the register contents from round mapping `from` to round mapping `to` through LDS.
-//
-// `flip` (tile-index bits of the `from` round's register bits) marks data held
-// at index t that logically belongs to t ^ flip; it is written to its logical
-// place, so the data arrives in the new mapping un-flipped.
 template <typename R, int LOGR>
-__device__ __forceinline__ void transpose(cx<R>* lds, cx<R> (&v)[1 << LOGR], uint32_t tid,
-                                          int from, int to, uint32_t flip = 0) {
-  const uint32_t s0 = swz<R>(tbase<LOGR>(tid, from) ^ flip);
+__device__ __forceinline__ void transpose(cx<R>* lds, cx<R> (&v)[1 << LOGR], uint32_t tid, int from, int to) {
+  const uint32_t s0 = swz<R>(tbase<LOGR>(tid, from));
 #pragma unroll
   for (int j = 0; j < (1 << LOGR); ++j) lds[s0 ^ swz<R>((uint32_t)j << from)] = v[j];
   __syncthreads();
@@ -150,6 +145,45 @@ __device__ __forceinline__ void transpose(cx<R>* lds, cx<R> (&v)[1 << LOGR], uin
 #pragma unroll
   for (int j = 0; j < (1 << LOGR); ++j) v[j] = lds[s1 ^ swz<R>((uint32_t)j << to)];
   __syncthreads();
+}
+
+// Half-tile transposes (complex64, 2^13-amplitude tiles): consecutive rounds'
+// register windows overlap in one tile bit s, so the tile splits into the two
+// halves s = 0 / s = 1 that move one after the other through 32 KiB of LDS
+// (index with bit s removed).  This halves the LDS a workgroup holds and lets
+// four workgroups share a CU.  The swizzle below spreads the 5 lane bits of
+// every such access over distinct banks (each high index bit XORs a chosen
+// bank-bit pattern into the low five bits; GF(2)-linear, a bijection).
+__device__ __forceinline__ uint32_t swz_half(uint32_t c) {
+  const uint32_t f = ((c >> 5) & 7u) ^ (((c >> 8) & 1u) * 24u) ^ (((c >> 9) & 1u) << 4) ^ ((c >> 10) & 3u);
+  return c ^ f;
+}
+__device__ __forceinline__ uint32_t drop_bit(uint32_t x, int s) {
+  return (x & ((1u << s) - 1u)) | ((x >> (s + 1)) << s);
+}
+template <typename R, int LOGR>
+__device__ __forceinline__ void transpose_half(cx<R>* lds, cx<R> (&v)[1 << LOGR], uint32_t tid, int from, int to) {
+  const int s = from > to ? from : to;   // the shared tile bit
+  const int kf = s - from, kt = s - to;  // its register bit in each round
+  const uint32_t cf = swz_half(drop_bit(tbase<LOGR>(tid, from), s));
+  const uint32_t ct = swz_half(drop_bit(tbase<LOGR>(tid, to), s));
+  // The first half's reads must not land on registers the second half still
+  // has to write out, so they go to a second array (register renaming in the
+  // unrolled code: no extra live registers).
+  cx<R> w[1 << LOGR];
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+    for (int j = 0; j < (1 << LOGR); ++j)
+      if (((j >> kf) & 1) == hh) lds[cf ^ swz_half(drop_bit((uint32_t)j << from, s))] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < (1 << LOGR); ++j)
+      if (((j >> kt) & 1) == hh) w[j] = lds[ct ^ swz_half(drop_bit((uint32_t)j << to, s))];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < (1 << LOGR); ++j) v[j] = w[j];
 }
 
 // exp(-i beta X) on a pair (a, b) = amplitudes differing only in that qubit.
@@ -309,27 +343,13 @@ __device__ __forceinline__ SiteVals site_values(const QCONST double* __restrict_
 // per-amplitude phase is exp(-i gamma C(z0)) * prod_{k in J} exp(-i gamma d_k)
 // * exp(-i gamma RT[J]); the product over J is split into a low and a high
 // half-tree so only 2^3 + 2^(LOGR-3) partial products stay in registers.
-// Site values seen from register slots whose logical register index is
-// J ^ f: C = cz0 + sum_{k in f} d_k + sum_{k in J} (+/-) d_k + RT[J ^ f].
-template <int LOGR>
-__device__ __forceinline__ SiteVals flip_site(const SiteVals& sv, uint32_t f) {
-  SiteVals r = sv;
-#pragma unroll
-  for (int k = 0; k < LOGR; ++k) {
-    const bool fk = (f >> k) & 1u;
-    r.cz0 += fk ? sv.d[k] : 0.0;
-    r.d[k] = fk ? -sv.d[k] : sv.d[k];
-  }
-  return r;
-}
-
 template <typename R, int LOGR>
 __device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVals& sv0, double gamma,
                                             const QCONST cx<R>* __restrict__ rtph, bool undo,
-                                            cx<R> pre = {(R)1, (R)0}, uint32_t f = 0) {
+                                            cx<R> pre = {(R)1, (R)0}) {
   constexpr int LO = LOGR < 3 ? LOGR : 3;
   constexpr int HI = LOGR - LO;
-  const SiteVals sv = flip_site<LOGR>(sv0, f);
+  const SiteVals& sv = sv0;
   const double gs = undo ? -gamma : gamma;
   cx<R> plo[1 << LO], phi[1 << HI];
   plo[0] = cmul(expmi<R>(gs * sv.cz0), pre);
@@ -348,7 +368,7 @@ __device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVal
   }
 #pragma unroll
   for (int j = 0; j < (1 << LOGR); ++j) {
-    const cx<R> rt = rtph[j ^ f];
+    const cx<R> rt = rtph[j];
     const cx<R> t = undo ? cmulc(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt)
                          : cmul(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt);
     v[j] = cmul(v[j], t);
@@ -384,11 +404,11 @@ __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
 //   with the cost phase, GEN synthesise |+>^n instead of loading, EXP 1 =
 //   accumulate <C> and the norm, 2 = also store lam = C psi.
 // With everything fixed the pass is straight-line code (no register merges).
-template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int EXP>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int EXP, int HALF>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(HALF ? 4 : 2, HALF ? 4 : 2)))
 k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   constexpr int NR = 1 << LOGR;
-  __shared__ cx<R> lds[1 << KB];
+  __shared__ cx<R> lds[1 << (KB - HALF)];
   __shared__ double red[2 * (kMaxThreads / 64)];
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
@@ -421,8 +441,13 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   if (need1)
     sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
 
+  // HALF: rounds are [K-LOGR, K), then each LOGR-1 lower (compile-time bases).
+  auto rbase = [&](int i) { return HALF ? KB - LOGR - i * (LOGR - 1) : D.rb[i]; };
+  auto step = [&](int from, int to) {
+    if (HALF) transpose_half<R, LOGR>(lds, v, tid, rbase(from), rbase(to));
+    else transpose<R, LOGR>(lds, v, tid, rbase(from), rbase(to));
+  };
   int cur = 0;
-  uint32_t fl = 0;   // pending index flips (tile bits) from shifted-angle segments
 #pragma unroll
   for (int s = 0; s < (NSC > 0 ? NSC : 64); ++s) {
     if (NSC <= 0 && s >= nseg) break;
@@ -430,30 +455,31 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
     if (PHM >= 0 ? ((PHM >> s) & 1) : sg.has_phase) {
       __builtin_amdgcn_sched_barrier(0);
       apply_phase<R, LOGR>(v, (s & 1) ? sv1 : sv0, sg.gamma, ctab + sg.ph_off, false,
-                           cx<R>{(R)sg.pre_re, (R)sg.pre_im}, fl >> D.rb[cur]);
+                           cx<R>{(R)sg.pre_re, (R)sg.pre_im});
       __builtin_amdgcn_sched_barrier(0);
     }
     const R t = (R)sg.coef;
-    const bool flips = sg.mode != 0;
 #pragma unroll
     for (int u = 0; u < (NRC > 0 ? NRC : kMaxRounds); ++u) {
       if (NRC <= 0 && u >= nr) break;
       const int i = (s & 1) ? nr - 1 - u : u;
       if (i != cur) {
-        transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[i], fl);
-        fl = 0;
+        step(cur, i);
         cur = i;
       }
       rx_round<R, LOGR>(v, D.rxmask[i], t);
       __builtin_amdgcn_sched_barrier(0);
-      if (flips) fl ^= (uint32_t)D.rxmask[i] << D.rb[i];
     }
   }
-  if (cur != 0) {
-    transpose<R, LOGR>(lds, v, tid, D.rb[cur], D.rb[0], fl);
-    fl = 0;
+  // back to round 0 for the coalesced store (adjacent steps for half tiles)
+  if (HALF) {
+#pragma unroll
+    for (int i = (NRC > 0 ? NRC : kMaxRounds) - 1; i > 0; --i)
+      if (i <= cur) step(i, i - 1);
+  } else if (cur != 0) {
+    step(cur, 0);
   }
-  const uint32_t f = fl >> D.rb[0];   // remaining flips: round-0 register bits
+
   if (flags & PF_SCALE) {
     const cx<R> fs = {(R)D.fscale_re, (R)D.fscale_im};
 #pragma unroll
@@ -462,9 +488,9 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
 
   if (exp > 0) {
     // Gray-code walk over the register index: one FP64 add per amplitude.
-    const SiteVals sv = flip_site<LOGR>(sv0, f);
+    const SiteVals& sv = sv0;
     const QCONST double* __restrict__ rt = dtab + D.site[0].rt_off;
-    QGLOBAL cx<R>* __restrict__ lam = gmem<cx<R>>(D.lam) + zt0;
+    QGLOBAL cx<R>* __restrict__ lam = gmem<cx<R>>(D.lam);
     double aE = 0.0, aN = 0.0, c = sv.cz0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
@@ -473,13 +499,13 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
         const int k = __builtin_ctz(i);
         c += ((J >> k) & 1) ? sv.d[k] : -sv.d[k];
       }
-      const double cj = c + rt[J ^ f];
+      const double cj = c + rt[J];
       const double pr = (double)v[J].re * v[J].re + (double)v[J].im * v[J].im;
       aE = fma(pr, cj, aE);
       aN += pr;
       if (exp == 2) {
         const cx<R> lv = {(R)(cj * v[J].re), (R)(cj * v[J].im)};
-        stg(lam + moff<LOGR>(J ^ f, D.rb[0], L, h), lv);
+        stg(lam + (zt0 | moff<LOGR>(J, D.rb[0], L, h)), lv);
       }
     }
     block_reduce2(aE, aN, red, blockDim.x);
@@ -489,11 +515,7 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
       part[D.ntiles + g] = aN;
     }
   }
-  if (!(flags & PF_NO_STORE)) {
-    QGLOBAL cx<R>* base = gmem<cx<R>>(D.psi) + zt0;
-#pragma unroll
-    for (int j = 0; j < NR; ++j) stg(base + moff<LOGR>(j ^ f, D.rb[0], L, h), v[j]);
-  }
+  if (!(flags & PF_NO_STORE)) store_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, D.rb[0], L, h);
 }
 
 // Im sum over register pairs of conj(l_a) f_b + conj(l_b) f_a, for the qubits in mask.
@@ -678,14 +700,15 @@ __global__ void k_cut_table_f64(const GraphDev* __restrict__ gp, double* __restr
 }
 
 // Per-block partials of Re<a|b>, Im<a|b>, <a|a>, <b|b> in FP64 (fixed grid).
+// rev_b: read b at the complemented index N-1-z.
 template <typename Ra, typename Rb>
 __global__ void __launch_bounds__(256) k_overlap(const cx<Ra>* __restrict__ a, const cx<Rb>* __restrict__ b,
-                                                 int64_t N, double* __restrict__ part) {
+                                                 int64_t N, double* __restrict__ part, int rev_b) {
   __shared__ double red[2 * 4];
   double sr = 0.0, si = 0.0, sa = 0.0, sb = 0.0;
   for (int64_t z = (int64_t)blockIdx.x * 256 + threadIdx.x; z < N; z += (int64_t)gridDim.x * 256) {
     const cx<Ra> x = ldg((const QGLOBAL cx<Ra>*)(a + z));
-    const cx<Rb> y = ldg((const QGLOBAL cx<Rb>*)(b + z));
+    const cx<Rb> y = ldg((const QGLOBAL cx<Rb>*)(b + (rev_b ? N - 1 - z : z)));
     const double ar = x.re, ai = x.im, br = y.re, bi = y.im;
     sr += ar * br + ai * bi;
     si += ar * bi - ai * br;
@@ -722,10 +745,11 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s, floa
 // ---------------------------------------------------------------------------
 template <typename R, int KB, int LOGR>
 static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, dim3 grid, dim3 block, hipStream_t st) {
+  constexpr int HALF = sizeof(R) == 4 ? 1 : 0;   // complex64 tiles move through half the LDS
   switch (shape) {
 #define QAOA_FWD(NRC, CODE, NSC, PHM, GEN, EXP)                                                              \
   case NRC * 8 + CODE:                                                                                      \
-    hipLaunchKernelGGL((k_fwd<R, LOGR, KB, NRC, NSC, PHM, GEN, EXP>), grid, block, 0, st, d, ndesc);        \
+    hipLaunchKernelGGL((k_fwd<R, LOGR, KB, NRC, NSC, PHM, GEN, EXP, HALF>), grid, block, 0, st, d, ndesc);  \
     return;
 #define QAOA_FWD_NR(NRC)                                      \
   QAOA_FWD(NRC, kShapeFirst, 1, 1, 1, 0)                      \
@@ -739,7 +763,7 @@ static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, dim3 grid
 #undef QAOA_FWD_NR
 #undef QAOA_FWD
     default:
-      hipLaunchKernelGGL((k_fwd<R, LOGR, KB, 0, 0, -1, -1, -1>), grid, block, 0, st, d, ndesc);
+      hipLaunchKernelGGL((k_fwd<R, LOGR, KB, 0, 0, -1, -1, -1, 0>), grid, block, 0, st, d, ndesc);
   }
 }
 
@@ -765,7 +789,7 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
     return hipGetLastError();
   }
 #define QAOA_GEN(LR) \
-  if (logr == LR) hipLaunchKernelGGL((k_fwd<R, LR, KB, 0, 0, -1, -1, -1>), grid, block, 0, st, d, ndesc);
+  if (logr == LR) hipLaunchKernelGGL((k_fwd<R, LR, KB, 0, 0, -1, -1, -1, 0>), grid, block, 0, st, d, ndesc);
   QAOA_GEN(1)
   QAOA_GEN(2)
   QAOA_GEN(3)
@@ -796,16 +820,39 @@ hipError_t launch_cut_table(const GraphDev* g, bool weighted, void* out, int64_t
 }
 
 hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, int64_t N, double* part,
-                          int nblocks, hipStream_t st) {
+                          int nblocks, int rev_b, hipStream_t st) {
   const dim3 grid(nblocks), block(256);
   if (prec_a == 1 && prec_b == 1)
-    hipLaunchKernelGGL((k_overlap<float, float>), grid, block, 0, st, (const cx<float>*)a, (const cx<float>*)b, N, part);
+    hipLaunchKernelGGL((k_overlap<float, float>), grid, block, 0, st, (const cx<float>*)a, (const cx<float>*)b, N, part,
+                       rev_b);
   else if (prec_a == 1)
-    hipLaunchKernelGGL((k_overlap<float, double>), grid, block, 0, st, (const cx<float>*)a, (const cx<double>*)b, N, part);
+    hipLaunchKernelGGL((k_overlap<float, double>), grid, block, 0, st, (const cx<float>*)a, (const cx<double>*)b, N,
+                       part, rev_b);
   else if (prec_b == 1)
-    hipLaunchKernelGGL((k_overlap<double, float>), grid, block, 0, st, (const cx<double>*)a, (const cx<float>*)b, N, part);
+    hipLaunchKernelGGL((k_overlap<double, float>), grid, block, 0, st, (const cx<double>*)a, (const cx<float>*)b, N,
+                       part, rev_b);
   else
-    hipLaunchKernelGGL((k_overlap<double, double>), grid, block, 0, st, (const cx<double>*)a, (const cx<double>*)b, N, part);
+    hipLaunchKernelGGL((k_overlap<double, double>), grid, block, 0, st, (const cx<double>*)a, (const cx<double>*)b, N,
+                       part, rev_b);
+  return hipGetLastError();
+}
+
+// In-place reversal z <-> N-1-z (the complement of every index bit): thread
+// i < N/2 swaps one pair, so no element is read after another thread wrote it.
+template <typename T>
+__global__ void __launch_bounds__(256) k_reverse(T* __restrict__ x, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N / 2) return;
+  const T a = x[i], b = x[N - 1 - i];
+  x[i] = b;
+  x[N - 1 - i] = a;
+}
+
+hipError_t launch_reverse(int prec, void* x, int64_t N, hipStream_t st) {
+  const int64_t blocks = (N / 2 + 255) / 256;
+  if (blocks < 1) return hipSuccess;
+  if (prec == 1) hipLaunchKernelGGL((k_reverse<float2>), dim3((unsigned)blocks), dim3(256), 0, st, (float2*)x, N);
+  else hipLaunchKernelGGL((k_reverse<double2>), dim3((unsigned)blocks), dim3(256), 0, st, (double2*)x, N);
   return hipGetLastError();
 }
 

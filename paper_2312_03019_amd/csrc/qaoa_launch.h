@@ -33,7 +33,9 @@ hipError_t launch_pass(int prec, bool backward, int logr, int shape, const PassD
 hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hipStream_t st);
 hipError_t launch_cut_table(const GraphDev* g, bool weighted, void* out, int64_t N, hipStream_t st);
 hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, int64_t N, double* part,
-                          int nblocks, hipStream_t st);
+                          int nblocks, int rev_b, hipStream_t st);
+// x[z] <-> x[N-1-z] in place (complements every index bit).
+hipError_t launch_reverse(int prec, void* x, int64_t N, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
 // Per-tile cut table (kTileCutStride doubles per tile) of one qubit set.
 hipError_t launch_tile_cut(const GraphDev* g, int K, int L, int h, int64_t ntiles, double* out, hipStream_t st);

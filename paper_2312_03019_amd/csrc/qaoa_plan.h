@@ -64,11 +64,13 @@ struct SiteDesc {
 // The forward sweep applies exp(-i beta X) = cos(beta) (I - i tan(beta) X)
 // (mode 0, |cos| >= |sin|) or, with b' = beta - pi/2,
 // (-i sin(beta)) X (I - i tan(b') X) (mode 1): always 4 FMAs per amplitude
-// pair with |t| <= 1.  Mode 1's X on each mixer qubit is an index flip the
-// kernel tracks and absorbs into LDS/HBM addresses.  The product sigma of the
-// factored scalars is carried on the host and folded into the next cost
-// phase (pre) or applied after the last pass (PassDesc::fscale).  The adjoint
-// sweep uses the unitary form (cb, sb).
+// pair with |t| <= 1.  All qubits of a layer share beta, so a mode-1 layer
+// leaves the state complemented on every qubit once it is complete; since
+// C(z) = C(~z) that commutes with every cost phase and leaves <C> unchanged,
+// and the run just records it (RunImage::complemented) when the count of
+// mode-1 layers is odd: the stored state is then psi(~z), i.e. reversed.  The product sigma of the factored scalars is carried on
+// the host and folded into the next cost phase (pre) or applied after the
+// last pass (PassDesc::fscale).  The adjoint sweep uses the unitary form.
 struct SegDesc {
   double gamma, beta;
   double cb, sb;            // cos(beta), sin(beta) in FP64

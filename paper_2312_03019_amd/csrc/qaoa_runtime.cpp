@@ -127,6 +127,10 @@ void build_dev_graph_image(const HostGraph& hg, void* host_buf, void* dev_base) 
   memcpy(h, &G, sizeof G);
 }
 
+bool half_tile_rounds(int K, int logr, const PrecCfg& pc) {
+  return pc.prec == 1 && K == kTileBitsC64 && logr == kLogRC64;
+}
+
 PrecCfg prec_cfg(int prec) {
   if (prec == QAOA_C64) return {1, kTileBitsC64, kLogRC64, kPassengerC64, 8};
   return {0, kTileBitsC128, kLogRC128, kPassengerC128, 16};
@@ -140,7 +144,9 @@ void tile_shape(int n, const PrecCfg& pc, int* K, int* logr) {
 // Rounds that put every tile bit of [sL, K) into registers once, starting
 // from the top tile bits (so round 0 leaves the low tile bits on lanes and
 // loads/stores coalesce).
-static void make_rounds(SetGeom& s, int sL, int logr) {
+// overlap: register windows of consecutive rounds share that many tile bits
+// (one for complex64 full-width tiles, which transpose through half the LDS).
+static void make_rounds(SetGeom& s, int sL, int logr, int overlap) {
   uint32_t want = 0, covered = 0;
   for (int t = sL; t < s.K; ++t) want |= 1u << t;
   int b = s.K - logr;
@@ -157,24 +163,25 @@ static void make_rounds(SetGeom& s, int sL, int logr) {
     ++s.nr;
     covered |= (uint32_t)mask << b;
     if ((covered & want) == want) break;
-    b -= logr;
+    b -= logr - overlap;
   }
 }
 
 std::vector<SetGeom> make_sets(int n, const PrecCfg& pc) {
   int K, logr;
   tile_shape(n, pc, &K, &logr);
+  const int ov = half_tile_rounds(K, logr, pc) ? 1 : 0;
   std::vector<SetGeom> sets;
   if (n <= pc.kmax) {
     SetGeom s{};
     s.K = n; s.L = n; s.h = n; s.k = n;
-    make_rounds(s, 0, logr);
+    make_rounds(s, 0, logr, ov);
     sets.push_back(s);
     return sets;
   }
   SetGeom a{};
   a.K = K; a.L = K; a.h = K; a.k = K;
-  make_rounds(a, 0, logr);
+  make_rounds(a, 0, logr, ov);
   sets.push_back(a);
   const int rem = n - K, cap = K - pc.passenger;
   const int mh = (rem + cap - 1) / cap;
@@ -184,7 +191,7 @@ std::vector<SetGeom> make_sets(int n, const PrecCfg& pc) {
     const int k = base + (i < extra ? 1 : 0);
     SetGeom s{};
     s.K = K; s.k = k; s.L = K - k; s.h = start;
-    make_rounds(s, s.L, logr);
+    make_rounds(s, s.L, logr, ov);
     sets.push_back(s);
     start += k;
   }
@@ -320,6 +327,9 @@ void build_run(const RunRequest& rq, RunImage* img) {
   // Mixer scalars still to be applied; folded into the next cost phase, or
   // applied at the end of the last pass.
   std::complex<double> pending(1.0, 0.0);
+  // parity of shifted-angle (mode 1) layers: the final state is complemented when odd
+  int mode1_layers = 0;
+  for (int l = 0; l < rq.p; ++l) mode1_layers += fabs(cos(rq.beta[l])) >= fabs(sin(rq.beta[l])) ? 0 : 1;
   int64_t part = 0;
   std::vector<int64_t> bwd_part(sched.size(), 0);
   int64_t fwd_part = 0;
@@ -432,6 +442,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
       img->bwd.push_back(b);
     }
   }
+  img->complemented = (mode1_layers & 1) != 0;
   // backward launches run from the last forward pass to the first
   std::reverse(img->bwd.begin(), img->bwd.end());
   img->part_doubles = part;

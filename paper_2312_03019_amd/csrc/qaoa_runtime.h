@@ -54,6 +54,10 @@ struct PrecCfg {
 };
 PrecCfg prec_cfg(int prec);
 
+// Whether a plan's rounds overlap by one tile bit (complex64 2^13 tiles,
+// moved through half the LDS by the specialised forward kernels).
+bool half_tile_rounds(int K, int logr, const PrecCfg& pc);
+
 // Tile bits and register bits used for an n-qubit state.
 void tile_shape(int n, const PrecCfg& pc, int* K, int* logr);
 std::vector<SetGeom> make_sets(int n, const PrecCfg& pc);
@@ -78,6 +82,7 @@ struct RunImage {
   int64_t part_doubles = 0;
   int nout = 0;
   std::vector<double> pass_bytes;    // algorithmic HBM bytes per forward pass
+  bool complemented = false;         // final state stored at z ^ (2^n - 1)
 };
 
 struct RunRequest {
