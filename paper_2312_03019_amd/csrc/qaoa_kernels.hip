@@ -405,7 +405,7 @@ __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
 //   accumulate <C> and the norm, 2 = also store lam = C psi.
 // With everything fixed the pass is straight-line code (no register merges).
 template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int EXP, int HALF>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(HALF ? 4 : 2, HALF ? 4 : 2)))
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(HALF ? 3 : 2, HALF ? 3 : 2)))
 k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   constexpr int NR = 1 << LOGR;
   __shared__ cx<R> lds[1 << (KB - HALF)];
@@ -442,8 +442,9 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
     sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
 
   // HALF: rounds are [K-LOGR, K), then each LOGR-1 lower (compile-time bases).
-  auto rbase = [&](int i) { return HALF ? KB - LOGR - i * (LOGR - 1) : D.rb[i]; };
-  auto step = [&](int from, int to) {
+  // (lambdas forced inline: an outlined call would move v[] to scratch memory)
+  auto rbase = [&](int i) __attribute__((always_inline)) { return HALF ? KB - LOGR - i * (LOGR - 1) : D.rb[i]; };
+  auto step = [&](int from, int to) __attribute__((always_inline)) {
     if (HALF) transpose_half<R, LOGR>(lds, v, tid, rbase(from), rbase(to));
     else transpose<R, LOGR>(lds, v, tid, rbase(from), rbase(to));
   };
