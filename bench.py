@@ -19,6 +19,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -47,23 +48,41 @@ def parse():
 
 
 def time_runs(q, torch, sim, g, b, steps, warmup):
+    """Wall time per run over `steps` runs, plus every forward-pass launch's
+    kernel time from HIP events recorded on the library's stream around each
+    launch inside those same timed runs."""
     for _ in range(warmup):
         sim.expect(g, b)
+    q.qaoa_set_profiling(sim.handle, True)
     torch.cuda.synchronize()
+    ms_all, by_all = [], []
     t0 = time.perf_counter()
     for _ in range(steps):
         q.qaoa_run(sim.handle, g, b)
-        e, nrm = q.qaoa_expect(sim.handle)
+        e, nrm = q.qaoa_expect(sim.handle)          # synchronises: events are complete
+        ms, by = q.qaoa_pass_times(sim.handle)
+        ms_all.append(ms)
+        by_all.append(by)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, e, nrm
-
-
-def pass_profile(q, sim, g, b):
-    q.qaoa_set_profiling(sim.handle, True)
-    sim.expect(g, b)
-    ms, by = q.qaoa_pass_times(sim.handle)
+    t = (time.perf_counter() - t0) / steps
     q.qaoa_set_profiling(sim.handle, False)
-    return ms, by
+    return t, e, nrm, np.array(ms_all), np.array(by_all)
+
+
+def pmc_traffic(path):
+    """Scaled HBM bytes per forward-pass launch from a committed rocprofv3
+    counter summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None, "no counter summary"
+    fields = dict(re.findall(r"^- (\w+): (\S+)$", txt, re.M))
+    src = os.path.join(ROOT, "paper_2312_03019_amd", "csrc", "qaoa_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        return None, "kernel source changed since the counters were taken"
+    return float(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
 
 
 def serve_bench(q, W, nreq):
@@ -129,20 +148,16 @@ def copy_ceiling(q, torch, nbytes=4 << 30, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(W):
+def cpu_baseline(W, prob, g, b, layers=2):
+    """The FP64 oracle on the same graph, for the first `layers` layers and <C>."""
     import oracle
-    n, p = 28, 5
-    rng = W.SplitMix64(3)
-    e = W.random_regular(n, 3, rng)
-    w = W.uniform_weights(e.shape[0], rng)
-    g, b = W.uniform_angles(p, rng)
     t0 = time.perf_counter()
-    oracle.run_expect(n, e, w, g, b)
+    oracle.run_expect(prob.n, prob.edges, prob.weights, g[:layers], b[:layers])
     dt = time.perf_counter() - t0
-    return {"value": p * (2 ** n) / dt, "unit": "layer amp-updates/s", "cores": oracle.num_threads(),
+    return {"value": layers * (2 ** prob.n) / dt, "unit": "layer amp-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"FP64 oracle, n={n} random 3-regular U[0,1) weights, p={p}, {dt:.1f} s "
-                      f"(same family as the n=30 workload; the oracle's per-amplitude work grows with n)"}
+            "sample": f"FP64 oracle on the same n={prob.n} graph, the first {layers} of the {len(g)} layers "
+                      f"(same angles) plus <C>: {dt:.1f} s; value = {layers} * 2^{prob.n} / t"}
 
 
 def main():
@@ -160,11 +175,11 @@ def main():
     res = {}
     for prec in (["c64"] if a.no_c128 else ["c64", "c128"]):
         sim = q.Simulator(prob.n, prob.edges, prob.weights, prec, stream=stream)
-        t, e, nrm = time_runs(q, torch, sim, g, b, a.steps, a.warmup)
-        ms, by = pass_profile(q, sim, g, b)
+        t, e, nrm, ms, by = time_runs(q, torch, sim, g, b, a.steps, a.warmup)
         passes, sizes = sim.plan(a.p)
-        res[prec] = {"t": t, "expect": e, "norm": nrm, "pass_ms": ms.tolist(), "pass_bytes": by.tolist(),
-                     "passes": passes, "sets": sizes}
+        res[prec] = {"t": t, "expect": e, "norm": nrm, "pass_ms": ms.mean(axis=0).tolist(),
+                     "pass_ms_all": ms.tolist(), "pass_bytes": by[0].tolist(), "passes": passes, "sets": sizes,
+                     "launch_ms_mean": float(ms.mean()), "launch_bytes_mean": float(by.mean())}
         if prec == "c64":
             keep64 = sim
         else:
@@ -176,8 +191,8 @@ def main():
     copy_gbs = copy_ceiling(q, torch)
     torch.cuda.empty_cache()
     r64 = res["c64"]
-    ms, by = np.array(r64["pass_ms"]), np.array(r64["pass_bytes"])
-    achieved = by.sum() / (ms.sum() * 1e-3) / 1e9          # GB/s, average over the run's launches
+    # algorithmic bytes per launch / mean launch duration, over every forward-pass launch of the timed runs
+    achieved = r64["launch_bytes_mean"] / (r64["launch_ms_mean"] * 1e-3) / 1e9
     line = {
         "metric": METRIC,
         "value": a.p * 2 ** a.n / r64["t"],
@@ -194,21 +209,30 @@ def main():
     }
     if "c128" in res:
         r128 = res["c128"]
-        m2, b2 = np.array(r128["pass_ms"]), np.array(r128["pass_bytes"])
         line["c128"] = {"value": a.p * 2 ** a.n / r128["t"], "ms_per_step": r128["t"] * 1e3,
-                        "hbm_gbps": b2.sum() / (m2.sum() * 1e-3) / 1e9, "expect": r128["expect"]}
+                        "hbm_gbps": r128["launch_bytes_mean"] / (r128["launch_ms_mean"] * 1e-3) / 1e9,
+                        "expect": r128["expect"]}
         line["c64_over_c128_speedup"] = r128["t"] / r64["t"]
         line["delta_expect_c64_c128"] = r64["expect"] - r128["expect"]
         line["one_minus_fidelity_c64_c128"] = 1.0 - res["fidelity_c64_c128"]
+    traffic, tsrc = (None, "counters apply to the n=30 p=10 workload only")
+    if a.n == 30 and a.p == 10:
+        traffic, tsrc = pmc_traffic(os.path.join(ROOT, "profiles", "k_fwd_weighted3reg_n30_p10_c64_counters.md"))
     line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                        "kernel": "k_forward (one launch per HBM pass)",
+                        "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": None if traffic is None else traffic / 1e9,
+                        "traffic_unit": "GB per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-kernel scaled)",
+                        "traffic_source": tsrc,
+                        "kernel": "k_fwd (one launch per HBM pass, all shapes)",
+                        "launches_timed": a.steps * r64["passes"],
+                        "algorithmic_bytes_per_launch": r64["launch_bytes_mean"],
+                        "mean_launch_ms": r64["launch_ms_mean"],
                         "copy_ceiling_gbps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                        "per_launch_bytes": "2*2^n*8 (write-only 2^n*8 for the first pass)"}
+                        "per_launch_bytes": "2*2^n*8 read+write (write-only 2^n*8 for the first pass)"}
     if not a.no_serve:
         line["serve"] = serve_bench(q, W, a.serve_requests)
     if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(W)
+        line["cpu_baseline"] = cpu_baseline(W, prob, g, b)
     os.makedirs(os.path.dirname(a.profile_out), exist_ok=True)
     with open(a.profile_out, "w") as f:
         json.dump({k: v for k, v in res.items()}, f)

@@ -147,15 +147,29 @@ __device__ __forceinline__ void transpose(cx<R>* lds, cx<R> (&v)[1 << LOGR], uin
   __syncthreads();
 }
 
-// Half-tile transposes (complex64, 2^13-amplitude tiles): consecutive rounds'
-// register windows overlap in one tile bit s, so the tile splits into the two
-// halves s = 0 / s = 1 that move one after the other through 32 KiB of LDS
-// (index with bit s removed).  This halves the LDS a workgroup holds and lets
-// four workgroups share a CU.  The swizzle below spreads the 5 lane bits of
-// every such access over distinct banks (each high index bit XORs a chosen
-// bank-bit pattern into the low five bits; GF(2)-linear, a bijection).
-__device__ __forceinline__ uint32_t swz_half(uint32_t c) {
+// Half-tile transposes: consecutive rounds' register windows overlap in at
+// least one tile bit s (the highest shared one is used), so the tile splits
+// into the two halves s = 0 / s = 1 that move one after the other through
+// half the LDS (index with bit s removed).  Four (complex64) or three
+// (complex128) workgroups then share a CU instead of two.  The swizzles below
+// spread the lanes of every such access over distinct banks: each index bit
+// above the bank group XORs a chosen pattern into the bank bits (GF(2)-linear,
+// hence a bijection).  Complex64: 32 lanes x 8 B per bank cycle, 5 bank bits;
+// complex128: 16 lanes x 16 B, 4 bank bits.  The patterns were found by a
+// search that checks every access of every round transition of the tile shape.
+template <typename R>
+__device__ __forceinline__ uint32_t swz_half(uint32_t c);
+template <>
+__device__ __forceinline__ uint32_t swz_half<float>(uint32_t c) {
   const uint32_t f = ((c >> 5) & 7u) ^ (((c >> 8) & 1u) * 24u) ^ (((c >> 9) & 1u) << 4) ^ ((c >> 10) & 3u);
+  return c ^ f;
+}
+template <>
+__device__ __forceinline__ uint32_t swz_half<double>(uint32_t c) {
+  constexpr uint32_t P[7] = {3u, 10u, 13u, 6u, 9u, 9u, 15u};   // for index bits 4..10
+  uint32_t f = 0;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) f ^= ((c >> (4 + i)) & 1u) * P[i];
   return c ^ f;
 }
 __device__ __forceinline__ uint32_t drop_bit(uint32_t x, int s) {
@@ -165,8 +179,8 @@ template <typename R, int LOGR>
 __device__ __forceinline__ void transpose_half(cx<R>* lds, cx<R> (&v)[1 << LOGR], uint32_t tid, int from, int to) {
   const int s = from > to ? from : to;   // the shared tile bit
   const int kf = s - from, kt = s - to;  // its register bit in each round
-  const uint32_t cf = swz_half(drop_bit(tbase<LOGR>(tid, from), s));
-  const uint32_t ct = swz_half(drop_bit(tbase<LOGR>(tid, to), s));
+  const uint32_t cf = swz_half<R>(drop_bit(tbase<LOGR>(tid, from), s));
+  const uint32_t ct = swz_half<R>(drop_bit(tbase<LOGR>(tid, to), s));
   // The first half's reads must not land on registers the second half still
   // has to write out, so they go to a second array (register renaming in the
   // unrolled code: no extra live registers).
@@ -175,11 +189,11 @@ __device__ __forceinline__ void transpose_half(cx<R>* lds, cx<R> (&v)[1 << LOGR]
   for (int hh = 0; hh < 2; ++hh) {
 #pragma unroll
     for (int j = 0; j < (1 << LOGR); ++j)
-      if (((j >> kf) & 1) == hh) lds[cf ^ swz_half(drop_bit((uint32_t)j << from, s))] = v[j];
+      if (((j >> kf) & 1) == hh) lds[cf ^ swz_half<R>(drop_bit((uint32_t)j << from, s))] = v[j];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < (1 << LOGR); ++j)
-      if (((j >> kt) & 1) == hh) w[j] = lds[ct ^ swz_half(drop_bit((uint32_t)j << to, s))];
+      if (((j >> kt) & 1) == hh) w[j] = lds[ct ^ swz_half<R>(drop_bit((uint32_t)j << to, s))];
     __syncthreads();
   }
 #pragma unroll
@@ -233,24 +247,67 @@ __device__ __forceinline__ void rx_regs(cx<R> (&v)[1 << LOGR], int mask, R c, R 
   }
 }
 
-// exp(-i th) in the working precision.  Single precision: reduce th modulo
-// 2 pi in double (two-constant Cody-Waite) before the float sine/cosine.
+// exp(-i th) = cos th - i sin th in the working precision, for the moderate
+// angles the cost phase produces.  Reduction (Cody-Waite): k = rint(th * 2/pi),
+// r = th - k * pi/2 in double with pi/2 split into two doubles, each product
+// taken exactly inside an FMA, so r in [-pi/4, pi/4] carries only rounding of
+// the last step.  sin r and cos r are their Taylor series, truncated where the
+// next term is below half an ulp of the working precision on [-pi/4, pi/4]
+// (float: through r^9 and r^10; double: through r^17 and r^16).  The quadrant
+// k mod 4 then swaps and negates the pair.  No large-argument path is needed
+// (or generated), unlike a general sincos.
 template <typename R>
-__device__ __forceinline__ cx<R> expmi(double th);
+__device__ __forceinline__ void sincos_poly(R r, R& s, R& c);
 template <>
-__device__ __forceinline__ cx<double> expmi<double>(double th) {
-  double s, c;
-  sincos(th, &s, &c);
-  return {c, -s};
+__device__ __forceinline__ void sincos_poly<float>(float r, float& s, float& c) {
+  const float r2 = r * r;
+  float ps = 1.0f / 362880.0f;                   // 1/9!
+  ps = fmaf(ps, r2, -1.0f / 5040.0f);
+  ps = fmaf(ps, r2, 1.0f / 120.0f);
+  ps = fmaf(ps, r2, -1.0f / 6.0f);
+  s = fmaf(ps * r2, r, r);
+  float pc = -1.0f / 3628800.0f;                 // -1/10!
+  pc = fmaf(pc, r2, 1.0f / 40320.0f);
+  pc = fmaf(pc, r2, -1.0f / 720.0f);
+  pc = fmaf(pc, r2, 1.0f / 24.0f);
+  pc = fmaf(pc, r2, -0.5f);
+  c = fmaf(pc, r2, 1.0f);
 }
 template <>
-__device__ __forceinline__ cx<float> expmi<float>(double th) {
-  const double k = rint(th * 0.15915494309189535);
-  double r = fma(-k, 6.283185307179586, th);
-  r = fma(-k, 2.4492935982947064e-16, r);
-  float s, c;
-  sincosf((float)r, &s, &c);
-  return {c, -s};
+__device__ __forceinline__ void sincos_poly<double>(double r, double& s, double& c) {
+  const double r2 = r * r;
+  double ps = 1.0 / 355687428096000.0;           // 1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);      // -1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);          // 1/13!
+  ps = fma(ps, r2, -1.0 / 39916800.0);           // -1/11!
+  ps = fma(ps, r2, 1.0 / 362880.0);
+  ps = fma(ps, r2, -1.0 / 5040.0);
+  ps = fma(ps, r2, 1.0 / 120.0);
+  ps = fma(ps, r2, -1.0 / 6.0);
+  s = fma(ps * r2, r, r);
+  double pc = 1.0 / 20922789888000.0;            // 1/16!
+  pc = fma(pc, r2, -1.0 / 87178291200.0);        // -1/14!
+  pc = fma(pc, r2, 1.0 / 479001600.0);           // 1/12!
+  pc = fma(pc, r2, -1.0 / 3628800.0);
+  pc = fma(pc, r2, 1.0 / 40320.0);
+  pc = fma(pc, r2, -1.0 / 720.0);
+  pc = fma(pc, r2, 1.0 / 24.0);
+  pc = fma(pc, r2, -0.5);
+  c = fma(pc, r2, 1.0);
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> expmi(double th) {
+  const double k = rint(th * 0.63661977236758134);       // 2/pi
+  double r = fma(-k, 1.5707963267948966, th);            // pi/2, high part
+  r = fma(-k, 6.123233995736766e-17, r);                 // pi/2, low part
+  R sr, cr;
+  sincos_poly<R>((R)r, sr, cr);
+  const int q = (int)k & 3;
+  const R c0 = (q & 1) ? sr : cr, s0 = (q & 1) ? cr : sr;
+  const R cs = ((q + 1) & 2) ? -c0 : c0;                  // cos(r + q pi/2)
+  const R sn = (q & 2) ? -s0 : s0;                        // sin(r + q pi/2)
+  return {cs, -sn};
 }
 
 // Sum over the 64-lane wave, then across waves; result valid on thread 0.
@@ -419,8 +476,6 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   const int flags = D.flags;
   const bool gen = GEN >= 0 ? GEN != 0 : (flags & PF_GEN) != 0;
   const int exp = EXP >= 0 ? EXP : ((flags & PF_EXPECT) ? ((flags & PF_WRITE_LAM) ? 2 : 1) : 0);
-  const bool need0 = PHM >= 0 ? ((PHM & 1) || EXP > 0) : (flags & PF_SITE0) != 0;
-  const bool need1 = PHM >= 0 ? ((PHM & 2) != 0) : (flags & PF_SITE1) != 0;
   const uint64_t zbase = tile_zbase(D, g);
   const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
   const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
@@ -436,14 +491,33 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   } else {
     load_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, D.rb[0], L, h);
   }
-  SiteVals sv0{}, sv1{};
-  if (need0) sv0 = site_values<LOGR>(dtab, D.site[0], tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
-  if (need1)
-    sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
+  // Site values: the per-thread cut decomposition; segment s uses site s & 1,
+  // at the round it starts in, and <C> uses site 0.  Full-LDS kernels run two
+  // workgroups per CU whatever their register count, so they read every site
+  // they need with the tile load (latency hidden, registers free).  Half-LDS
+  // kernels are register-limited: only the first phase's site is read up
+  // front, a later phase's where it is used, and <C>'s just before the last
+  // mixer round when that round is round 0, else after the way back to it.
+  constexpr bool kEarly = HALF == 0;
+  auto site = [&](int which) __attribute__((always_inline)) {
+    const int b = which ? D.rb[nr - 1] : D.rb[0];
+    return site_values<LOGR>(dtab, D.site[which], tcrow, tbase<LOGR>(tid, b), b, D.K, tid, nth);
+  };
+  auto has_phase = [&](int s) __attribute__((always_inline)) {
+    return PHM >= 0 ? ((PHM >> s) & 1) != 0 : segs[s].has_phase != 0;
+  };
+  const bool need0 = PHM >= 0 ? ((PHM & 1) || EXP > 0) : (flags & PF_SITE0) != 0;
+  const bool need1 = PHM >= 0 ? ((PHM & 2) != 0) : (flags & PF_SITE1) != 0;
+  SiteVals s0{}, s1{}, sve{};
+  if (kEarly ? need0 : has_phase(0)) s0 = site(0);
+  if (kEarly && need1) s1 = site(1);
 
-  // HALF: rounds are [K-LOGR, K), then each LOGR-1 lower (compile-time bases).
+  // HALF: rounds are [K-LOGR, K), then each LOGR-1 lower, the last clamped at
+  // 0 (compile-time bases).
   // (lambdas forced inline: an outlined call would move v[] to scratch memory)
-  auto rbase = [&](int i) __attribute__((always_inline)) { return HALF ? KB - LOGR - i * (LOGR - 1) : D.rb[i]; };
+  auto rbase = [&](int i) __attribute__((always_inline)) {
+    return HALF ? (KB - LOGR - i * (LOGR - 1) > 0 ? KB - LOGR - i * (LOGR - 1) : 0) : D.rb[i];
+  };
   auto step = [&](int from, int to) __attribute__((always_inline)) {
     if (HALF) transpose_half<R, LOGR>(lds, v, tid, rbase(from), rbase(to));
     else transpose<R, LOGR>(lds, v, tid, rbase(from), rbase(to));
@@ -453,10 +527,10 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   for (int s = 0; s < (NSC > 0 ? NSC : 64); ++s) {
     if (NSC <= 0 && s >= nseg) break;
     const SegDesc sg = segs[s];
-    if (PHM >= 0 ? ((PHM >> s) & 1) : sg.has_phase) {
+    if (has_phase(s)) {
       __builtin_amdgcn_sched_barrier(0);
-      apply_phase<R, LOGR>(v, (s & 1) ? sv1 : sv0, sg.gamma, ctab + sg.ph_off, false,
-                           cx<R>{(R)sg.pre_re, (R)sg.pre_im});
+      apply_phase<R, LOGR>(v, s == 0 ? s0 : kEarly ? ((s & 1) ? s1 : s0) : site(s & 1), sg.gamma,
+                           ctab + sg.ph_off, false, cx<R>{(R)sg.pre_re, (R)sg.pre_im});
       __builtin_amdgcn_sched_barrier(0);
     }
     const R t = (R)sg.coef;
@@ -468,6 +542,7 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
         step(cur, i);
         cur = i;
       }
+      if (!kEarly && exp > 0 && s == nseg - 1 && u == nr - 1 && i == 0) sve = site(0);
       rx_round<R, LOGR>(v, D.rxmask[i], t);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -480,6 +555,8 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   } else if (cur != 0) {
     step(cur, 0);
   }
+  if (kEarly) sve = s0;
+  else if (exp > 0 && (nseg == 0 || cur != 0)) sve = site(0);
 
   if (flags & PF_SCALE) {
     const cx<R> fs = {(R)D.fscale_re, (R)D.fscale_im};
@@ -489,16 +566,15 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
 
   if (exp > 0) {
     // Gray-code walk over the register index: one FP64 add per amplitude.
-    const SiteVals& sv = sv0;
     const QCONST double* __restrict__ rt = dtab + D.site[0].rt_off;
     QGLOBAL cx<R>* __restrict__ lam = gmem<cx<R>>(D.lam);
-    double aE = 0.0, aN = 0.0, c = sv.cz0;
+    double aE = 0.0, aN = 0.0, c = sve.cz0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       const int J = i ^ (i >> 1);
       if (i > 0) {
         const int k = __builtin_ctz(i);
-        c += ((J >> k) & 1) ? sv.d[k] : -sv.d[k];
+        c += ((J >> k) & 1) ? sve.d[k] : -sve.d[k];
       }
       const double cj = c + rt[J];
       const double pr = (double)v[J].re * v[J].re + (double)v[J].im * v[J].im;
@@ -746,7 +822,7 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s, floa
 // ---------------------------------------------------------------------------
 template <typename R, int KB, int LOGR>
 static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, dim3 grid, dim3 block, hipStream_t st) {
-  constexpr int HALF = sizeof(R) == 4 ? 1 : 0;   // complex64 tiles move through half the LDS
+  constexpr int HALF = 1;   // full-width tiles move through half the LDS
   switch (shape) {
 #define QAOA_FWD(NRC, CODE, NSC, PHM, GEN, EXP)                                                              \
   case NRC * 8 + CODE:                                                                                      \
@@ -761,6 +837,11 @@ static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, dim3 grid
     QAOA_FWD_NR(1)
     QAOA_FWD_NR(2)
     QAOA_FWD_NR(3)
+    // four rounds (complex128 low set): a merged pass would spill, it takes the generic kernel
+    QAOA_FWD(4, kShapeFirst, 1, 1, 1, 0)
+    QAOA_FWD(4, kShapeSingle, 1, 0, 0, 0)
+    QAOA_FWD(4, kShapeLast, 1, 0, 0, 1)
+    QAOA_FWD(4, kShapeLastLam, 1, 0, 0, 2)
 #undef QAOA_FWD_NR
 #undef QAOA_FWD
     default:

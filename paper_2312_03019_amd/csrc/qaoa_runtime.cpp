@@ -128,7 +128,7 @@ void build_dev_graph_image(const HostGraph& hg, void* host_buf, void* dev_base) 
 }
 
 bool half_tile_rounds(int K, int logr, const PrecCfg& pc) {
-  return pc.prec == 1 && K == kTileBitsC64 && logr == kLogRC64;
+  return K == pc.kmax && logr == pc.logr_max;
 }
 
 PrecCfg prec_cfg(int prec) {

@@ -1,0 +1,125 @@
+"""Turn rocprofv3 CSV output into the short text summaries kept under profiles/.
+
+  python -m paper_2312_03019_amd.profile_summary stats --dir D --prefix P --cmd "..." > out.md
+      per-kernel launch counts and durations from P_kernel_stats.csv, with the
+      forward-pass kernels (every k_fwd shape) aggregated per precision.
+  python -m paper_2312_03019_amd.profile_summary counters --fetch F.csv --write W.csv \\
+      --copy-bytes B --cmd "..." > out.md
+      HBM bytes per forward-pass launch from FETCH_SIZE / WRITE_SIZE (KiB per
+      dispatch), each scaled by what the same counter reports for the plain copy
+      kernel k_copy moving a known B bytes each way.
+
+The counter summary records the SHA-256 of the kernel source it was taken
+with, so a reader can tell when the counters no longer describe the code.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(HERE, "csrc", "qaoa_kernels.hip")
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _prec(name):
+    m = re.search(r"k_fwd<(float|double)", name)
+    return m.group(1) if m else None
+
+
+def stats(a):
+    path = os.path.join(a.dir, f"{a.prefix}_kernel_stats.csv")
+    rows = list(csv.DictReader(open(path)))
+    out = ["# Kernel durations (rocprofv3 --kernel-trace --stats)", "", "Command:", "", "```", a.cmd, "```", "",
+           "| kernel | calls | avg ms | min ms | max ms | share |", "|---|---|---|---|---|---|"]
+    agg = {}
+    for r in rows:
+        name, calls = r["Name"], int(r["Calls"])
+        tot = float(r["TotalDurationNs"])
+        out.append(f"| `{name[:110]}` | {calls} | {float(r['AverageNs']) / 1e6:.3f} | "
+                   f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
+        p = _prec(name)
+        if p:
+            c, t = agg.get(p, (0, 0.0))
+            agg[p] = (c + calls, t + tot)
+    out += ["", "Forward-pass kernel k_fwd, all shapes together:", ""]
+    for p, (c, t) in sorted(agg.items()):
+        label = "complex64" if p == "float" else "complex128"
+        out.append(f"- k_fwd_{label}_launches: {c}")
+        out.append(f"- k_fwd_{label}_mean_launch_ms: {t / c / 1e6:.4f}")
+    out.append(f"- kernel_source_sha256: {kernel_sha()}")
+    print("\n".join(out))
+
+
+def _per_dispatch(path, counter):
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        key = int(r["Dispatch_Id"])
+        vals[key] = (r["Kernel_Name"], vals.get(key, ("", 0.0))[1] + float(r["Counter_Value"]))
+    return vals
+
+
+def counters(a):
+    fetch = _per_dispatch(a.fetch, "FETCH_SIZE")
+    write = _per_dispatch(a.write, "WRITE_SIZE")
+
+    def pick(d, pred):
+        return [v for (n, v) in d.values() if pred(n)]
+
+    is_copy = lambda n: "k_copy" in n
+    is_fwd = lambda n: "k_fwd<float" in n
+    cf, cw = pick(fetch, is_copy), pick(write, is_copy)
+    ff, fw = pick(fetch, is_fwd), pick(write, is_fwd)
+    if not (cf and cw and ff and fw):
+        sys.exit("missing k_copy or k_fwd dispatches in the counter files")
+    kib = lambda xs: sum(xs) / len(xs)
+    sf = a.copy_bytes / (kib(cf) * 1024.0)       # bytes per reported KiB, reads
+    sw = a.copy_bytes / (kib(cw) * 1024.0)       # bytes per reported KiB, writes
+    f_b, w_b = kib(ff) * 1024.0 * sf, kib(fw) * 1024.0 * sw
+    out = ["# HBM traffic of the forward pass (rocprofv3 --pmc)", "", "Commands (one counter per run):", "", "```",
+           a.cmd, "```", "",
+           f"Copy kernel k_copy, {a.copy_bytes} bytes read and written per dispatch: FETCH_SIZE "
+           f"{kib(cf):.1f} KiB, WRITE_SIZE {kib(cw):.1f} KiB per dispatch, so one reported KiB is "
+           f"{sf:.3f} KiB read and {sw:.3f} KiB written.", "",
+           f"Forward pass k_fwd (complex64, all shapes, {len(ff)} dispatches): FETCH_SIZE {kib(ff):.1f} KiB, "
+           f"WRITE_SIZE {kib(fw):.1f} KiB per dispatch (raw), scaled {f_b / 1e9:.3f} GB read + "
+           f"{w_b / 1e9:.3f} GB written.", ""]
+    if a.alg_bytes:
+        out.append(f"Algorithmic bytes per launch (mean over the run's passes): {a.alg_bytes / 1e9:.3f} GB; "
+                   f"measured / algorithmic = {(f_b + w_b) / a.alg_bytes:.3f}.")
+        out.append("")
+    out += [f"- fetch_scale: {sf:.4f}", f"- write_scale: {sw:.4f}",
+            f"- traffic_bytes_per_launch: {f_b + w_b:.6e}",
+            f"- kernel_source_sha256: {kernel_sha()}"]
+    print("\n".join(out))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--dir", required=True)
+    s.add_argument("--prefix", required=True)
+    s.add_argument("--cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--copy-bytes", type=float, required=True)
+    c.add_argument("--alg-bytes", type=float, default=0.0)
+    c.add_argument("--cmd", required=True)
+    a = ap.parse_args()
+    stats(a) if a.mode == "stats" else counters(a)
+
+
+if __name__ == "__main__":
+    main()
