@@ -215,10 +215,13 @@ __device__ __forceinline__ void bfly(cx<R>& a, cx<R>& b, R c, R s) {
 // identity, so the code has no data-dependent branches.  The dropped scalar
 // per qubit (cos beta, or -i sin beta when the segment uses the shifted
 // angle) is applied once per segment elsewhere.
+// `cand` (a compile-time constant in the half-tile kernels) lists the bits
+// that can be in the mask at all; the others generate no code.
 template <typename R, int LOGR>
-__device__ __forceinline__ void rx_round(cx<R> (&v)[1 << LOGR], int mask, R t) {
+__device__ __forceinline__ void rx_round(cx<R> (&v)[1 << LOGR], int mask, R t, int cand = (1 << LOGR) - 1) {
 #pragma unroll
   for (int k = 0; k < LOGR; ++k) {
+    if (!((cand >> k) & 1)) continue;
     const R tk = ((mask >> k) & 1) ? t : (R)0;
 #pragma unroll
     for (int j = 0; j < (1 << LOGR); ++j) {
@@ -543,7 +546,10 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
         cur = i;
       }
       if (!kEarly && exp > 0 && s == nseg - 1 && u == nr - 1 && i == 0) sve = site(0);
-      rx_round<R, LOGR>(v, D.rxmask[i], t);
+      // Half tiles: round i > 0 shares its top bits with round i-1, which
+      // mixed them (the masks give each qubit to the first round holding it).
+      const int cand = (HALF && i > 0) ? ((1 << LOGR) - 1) >> (rbase(i) + LOGR - rbase(i - 1)) : (1 << LOGR) - 1;
+      rx_round<R, LOGR>(v, D.rxmask[i], t, cand);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -837,9 +843,10 @@ static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, dim3 grid
     QAOA_FWD_NR(1)
     QAOA_FWD_NR(2)
     QAOA_FWD_NR(3)
-    // four rounds (complex128 low set): a merged pass would spill, it takes the generic kernel
+    // Four rounds (the complex128 low set): a merged pass would spill and a
+    // plain single pass is faster through the full LDS (it already streams at
+    // copy speed there), so those two take the generic kernel.
     QAOA_FWD(4, kShapeFirst, 1, 1, 1, 0)
-    QAOA_FWD(4, kShapeSingle, 1, 0, 0, 0)
     QAOA_FWD(4, kShapeLast, 1, 0, 0, 1)
     QAOA_FWD(4, kShapeLastLam, 1, 0, 0, 2)
 #undef QAOA_FWD_NR

@@ -293,14 +293,19 @@ static SiteDesc make_site(const SetGeom& s, int round, int logr, const HostGraph
 }
 
 // Which specialised forward kernel runs a pass (0 = the generic one).
-static int forward_shape(const PassDesc& d, bool full_width, const SegDesc* segs) {
-  if (!full_width || d.nrounds < 1 || d.nrounds > 3) return 0;
+// Compiled pass shapes exist for full-width tiles (K and LOGR at their
+// maxima), whose rounds follow the half-tile pattern: [K-LOGR, K), then each
+// LOGR-1 lower, the last clamped at 0.  Anything else takes the generic kernel.
+static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const SegDesc* segs) {
+  if (d.K != pc.kmax || logr != pc.logr_max || d.nrounds < 1 || d.nrounds > 4) return 0;
+  for (int i = 0; i < d.nrounds; ++i)
+    if (d.rb[i] != std::max(0, d.K - logr - i * (logr - 1))) return 0;
   const bool gen = d.flags & PF_GEN, ex = d.flags & PF_EXPECT, lam = d.flags & PF_WRITE_LAM;
   const bool ph0 = d.nseg >= 1 && segs[0].has_phase, ph1 = d.nseg >= 2 && segs[1].has_phase;
   int code = 0;
   if (d.nseg == 1 && gen && ph0 && !ex) code = kShapeFirst;
-  else if (d.nseg == 1 && !gen && !ph0 && !ex) code = kShapeSingle;
-  else if (d.nseg == 2 && !gen && !ph0 && ph1 && !ex) code = kShapeMerged;
+  else if (d.nseg == 1 && !gen && !ph0 && !ex && d.nrounds <= 3) code = kShapeSingle;
+  else if (d.nseg == 2 && !gen && !ph0 && ph1 && !ex && d.nrounds <= 3) code = kShapeMerged;
   else if (d.nseg == 1 && !gen && !ph0 && ex) code = lam ? kShapeLastLam : kShapeLast;
   return code ? d.nrounds * 8 + code : 0;
 }
@@ -414,7 +419,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
     if (ph_even || ps.expect) fflags |= PF_SITE0;
     if (ph_odd) fflags |= PF_SITE1;
     d.flags |= fflags;
-    d.shape = forward_shape(d, logr == pc.logr_max, img->segs.data() + seg0);
+    d.shape = forward_shape(d, pc, logr, img->segs.data() + seg0);
     d.psi = rq.psi;
     d.lam = rq.lam;
     d.g = rq.g;

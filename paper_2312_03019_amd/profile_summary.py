@@ -8,6 +8,8 @@
       HBM bytes per forward-pass launch from FETCH_SIZE / WRITE_SIZE (KiB per
       dispatch), each scaled by what the same counter reports for the plain copy
       kernel k_copy moving a known B bytes each way.
+  python -m paper_2312_03019_amd.profile_summary table --csv C.csv --cmd "..." > out.md
+      per-dispatch averages of every counter in one --pmc run, per kernel.
 
 The counter summary records the SHA-256 of the kernel source it was taken
 with, so a reader can tell when the counters no longer describe the code.
@@ -104,6 +106,26 @@ def counters(a):
     print("\n".join(out))
 
 
+def table(a):
+    sums, calls = {}, {}
+    for r in csv.DictReader(open(a.csv)):
+        name = r["Kernel_Name"]
+        if "k_fwd" not in name and "k_copy" not in name:
+            continue
+        d = sums.setdefault(name, {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        calls.setdefault(name, set()).add(r["Dispatch_Id"])
+    names = sorted({c for d in sums.values() for c in d})
+    out = ["# Shader counters per dispatch (rocprofv3 --pmc)", "", "Command:", "", "```", a.cmd, "```", "",
+           "| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for name, d in sums.items():
+        c = len(calls[name])
+        out.append(f"| `{name[:80]}` | {c} | " + " | ".join(f"{d.get(k, 0.0) / c:.4g}" for k in names) + " |")
+    out.append("")
+    out.append(f"- kernel_source_sha256: {kernel_sha()}")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -117,8 +139,11 @@ def main():
     c.add_argument("--copy-bytes", type=float, required=True)
     c.add_argument("--alg-bytes", type=float, default=0.0)
     c.add_argument("--cmd", required=True)
+    t = sub.add_parser("table")
+    t.add_argument("--csv", required=True)
+    t.add_argument("--cmd", required=True)
     a = ap.parse_args()
-    stats(a) if a.mode == "stats" else counters(a)
+    {"stats": stats, "counters": counters, "table": table}[a.mode](a)
 
 
 if __name__ == "__main__":
