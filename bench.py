@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--profile-out", default=os.path.join(ROOT, "gpurun_out", "bench_passes.json"))
     return ap.parse_args()
 
@@ -127,6 +128,33 @@ def serve_bench(q, W, nreq):
     out["requests"] = nreq
     out["workload"] = ("Poisson arrivals; family uniform {3-regular (even n), G(n,0.3), complete}; "
                        "n U{14..28}; weights U[0,1); p U{1..12}; 30% gradient; complex64; budget 200 GiB")
+    return out
+
+
+def grad_bench(q, torch, W):
+    """Adjoint gradients on the n=24 G(24, 0.3) p=8 workload, 64 parameter sets."""
+    prob, params = W.grad_gnp_n24()
+    out = {"workload": "n=24 G(24,0.3) unweighted (seed 4), p=8, 64 parameter sets U[0,pi); "
+                       "state 128/256 MiB (cache-resident, not an HBM roofline point)"}
+    for prec in ("c64", "c128"):
+        sim = q.Simulator(prob.n, prob.edges, None, prec)
+        sim.grad(*params[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g, b in params:
+            sim.grad(g, b)
+        t = time.perf_counter() - t0
+        q.qaoa_set_profiling(sim.handle, True)
+        sim.grad(*params[0])
+        ms, by = q.qaoa_pass_times(sim.handle)
+        q.qaoa_set_profiling(sim.handle, False)
+        passes, _ = sim.plan(len(params[0][0]))
+        fm, fb, bm, bb = ms[:passes], by[:passes], ms[passes:], by[passes:]
+        out[prec] = {"grads_per_s": len(params) / t, "ms_per_grad": 1e3 * t / len(params),
+                     "forward_gbps": fb.sum() / (fm.sum() * 1e-3) / 1e9,
+                     "backward_gbps": bb.sum() / (bm.sum() * 1e-3) / 1e9 if len(bm) else None,
+                     "forward_ms": float(fm.sum()), "backward_ms": float(bm.sum())}
+        sim.close()
     return out
 
 
@@ -229,6 +257,8 @@ def main():
                         "mean_launch_ms": r64["launch_ms_mean"],
                         "copy_ceiling_gbps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                         "per_launch_bytes": "2*2^n*8 read+write (write-only 2^n*8 for the first pass)"}
+    if not a.no_grad:
+        line["grad"] = grad_bench(q, torch, W)
     if not a.no_serve:
         line["serve"] = serve_bench(q, W, a.serve_requests)
     if not a.no_cpu:

@@ -122,10 +122,12 @@ int qaoa_bind_state(qaoa_ctx *ctx, void *dev_ptr, size_t bytes);
  * bracketed by HIP events on the bound stream. */
 int qaoa_set_profiling(qaoa_ctx *ctx, int enable);
 
-/* Kernel times (ms) of the passes of the last run, in launch order, plus each
- * pass's algorithmic HBM bytes (state bytes read + written).  Fills at most
- * max entries of ms[] and bytes[] (either may be NULL) and returns the pass
- * count through *count.  Synchronises the stream. */
+/* Kernel times (ms) of the passes of the last run, in launch order (the
+ * forward passes, then after qaoa_grad the backward passes), plus each pass's
+ * algorithmic HBM bytes (state bytes read + written, both vectors for a
+ * backward pass).  Fills at most max entries of ms[] and bytes[] (either may
+ * be NULL) and returns the pass count through *count.  Synchronises the
+ * stream.  Only runs made while profiling is enabled are timed. */
 int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count);
 
 /* Plan of a run of depth p: number of HBM passes, number of qubit sets the

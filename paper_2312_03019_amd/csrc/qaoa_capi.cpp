@@ -164,9 +164,9 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
   tile_shape(c->hg.n, pc, &K, &logr);
   const int nthreads = 1 << (K - logr);
   const int64_t ntiles = (int64_t)1 << (c->hg.n - K);
-  const size_t nf = img.fwd.size();
+  const size_t nf = img.fwd.size(), nb = img.bwd.size();
   if (c->profiling) {
-    while (c->ev.size() < 2 * nf) {
+    while (c->ev.size() < 2 * (nf + nb)) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e));
       c->ev.push_back(e);
@@ -178,11 +178,15 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
     HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[i].shape, dfwd + i, 1, ntiles, nthreads, c->stream));
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * i + 1], c->stream));
   }
-  c->ntimed = c->profiling ? (int)nf : 0;
+  c->ntimed = c->profiling ? (int)(nf + nb) : 0;
   c->pass_bytes = img.pass_bytes;
+  c->pass_bytes.insert(c->pass_bytes.end(), img.bwd_bytes.begin(), img.bwd_bytes.end());
   const PassDesc* dbwd = (const PassDesc*)(c->dev_img + lay.off_bwd);
-  for (size_t i = 0; i < img.bwd.size(); ++i)
+  for (size_t i = 0; i < nb; ++i) {
+    if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * (nf + i)], c->stream));
     HIPCHK(launch_pass(pc.prec, true, logr, 0, dbwd + i, 1, ntiles, nthreads, c->stream));
+    if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * (nf + i) + 1], c->stream));
+  }
   HIPCHK(launch_reduce((const ReduceJob*)(c->dev_img + lay.off_jobs), (const Span*)(c->dev_img + lay.off_spans),
                        (int)img.jobs.size(), c->stream));
   HIPCHK(hipMemcpyAsync(c->host_out, c->dev_out, img.nout * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -150,13 +150,14 @@ __device__ __forceinline__ void transpose(cx<R>* lds, cx<R> (&v)[1 << LOGR], uin
 // Half-tile transposes: consecutive rounds' register windows overlap in at
 // least one tile bit s (the highest shared one is used), so the tile splits
 // into the two halves s = 0 / s = 1 that move one after the other through
-// half the LDS (index with bit s removed).  Four (complex64) or three
-// (complex128) workgroups then share a CU instead of two.  The swizzles below
-// spread the lanes of every such access over distinct banks: each index bit
-// above the bank group XORs a chosen pattern into the bank bits (GF(2)-linear,
-// hence a bijection).  Complex64: 32 lanes x 8 B per bank cycle, 5 bank bits;
-// complex128: 16 lanes x 16 B, 4 bank bits.  The patterns were found by a
-// search that checks every access of every round transition of the tile shape.
+// half the LDS (index with bit s removed).  Three workgroups then share a CU
+// (the register budget of three waves per SIMD) instead of two.  The swizzles
+// below spread the lanes of every such access over distinct banks: each index
+// bit above the bank group XORs a chosen pattern into the bank bits
+// (GF(2)-linear, hence a bijection).  Complex64: 32 lanes x 8 B per bank
+// cycle, 5 bank bits; complex128: 16 lanes x 16 B, 4 bank bits.  Both were
+// checked against every access of every round transition of the tile shape
+// (the complex128 pattern was found by a search over such patterns).
 template <typename R>
 __device__ __forceinline__ uint32_t swz_half(uint32_t c);
 template <>

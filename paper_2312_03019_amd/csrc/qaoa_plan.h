@@ -68,9 +68,10 @@ struct SiteDesc {
 // leaves the state complemented on every qubit once it is complete; since
 // C(z) = C(~z) that commutes with every cost phase and leaves <C> unchanged,
 // and the run just records it (RunImage::complemented) when the count of
-// mode-1 layers is odd: the stored state is then psi(~z), i.e. reversed.  The product sigma of the factored scalars is carried on
-// the host and folded into the next cost phase (pre) or applied after the
-// last pass (PassDesc::fscale).  The adjoint sweep uses the unitary form.
+// mode-1 layers is odd: the stored state is then psi(~z), i.e. reversed.
+// The product sigma of the factored scalars is carried on the host and
+// folded into the next cost phase (pre) or applied after the last pass
+// (PassDesc::fscale).  The adjoint sweep uses the unitary form.
 struct SegDesc {
   double gamma, beta;
   double cb, sb;            // cos(beta), sin(beta) in FP64

@@ -145,7 +145,7 @@ void tile_shape(int n, const PrecCfg& pc, int* K, int* logr) {
 // from the top tile bits (so round 0 leaves the low tile bits on lanes and
 // loads/stores coalesce).
 // overlap: register windows of consecutive rounds share that many tile bits
-// (one for complex64 full-width tiles, which transpose through half the LDS).
+// (one for full-width tiles, which transpose through half the LDS).
 static void make_rounds(SetGeom& s, int sL, int logr, int overlap) {
   uint32_t want = 0, covered = 0;
   for (int t = sL; t < s.K; ++t) want |= 1u << t;
@@ -445,11 +445,13 @@ void build_run(const RunRequest& rq, RunImage* img) {
       b.part = (double*)(intptr_t)part;
       part += 2 * (int64_t)d.nseg * ntiles;
       img->bwd.push_back(b);
+      img->bwd_bytes.push_back(ps.gen ? 2.0 * state_bytes : 4.0 * state_bytes);   // phi and lam
     }
   }
   img->complemented = (mode1_layers & 1) != 0;
   // backward launches run from the last forward pass to the first
   std::reverse(img->bwd.begin(), img->bwd.end());
+  std::reverse(img->bwd_bytes.begin(), img->bwd_bytes.end());
   img->part_doubles = part;
 
   // outputs: [E, N, dgamma[p], dbeta[p]]

@@ -82,6 +82,7 @@ struct RunImage {
   int64_t part_doubles = 0;
   int nout = 0;
   std::vector<double> pass_bytes;    // algorithmic HBM bytes per forward pass
+  std::vector<double> bwd_bytes;     // ... and per backward pass
   bool complemented = false;         // final state stored at z ^ (2^n - 1)
 };
 

@@ -1,0 +1,60 @@
+"""Write tests/golden/oracle_fullsize.json: FP64 oracle results at the full
+workload sizes, which the oracle needs minutes to produce (too slow to rerun
+inside the GPU tests).  Every value comes from oracle/ alone, on the seeded
+inputs of workloads/:
+
+  gnp_n26          G(26, 0.5) unweighted, p = 4: <C> and the norm
+  weighted_3reg_n30  random 3-regular, U[0,1) weights, n = 30, p = 10: <C>, norm
+  grad_gnp_n24     G(24, 0.3) unweighted, p = 8, 64 parameter sets: <C> and
+                   the adjoint gradient (16 values) of every set
+
+Usage: python tests/golden/make_golden.py [--skip-n30]   (n = 30 needs ~24 GiB RAM)
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads as W  # noqa: E402
+
+OUT = os.path.join(HERE, "oracle_fullsize.json")
+
+
+def main():
+    skip30 = "--skip-n30" in sys.argv
+    out = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    out["_about"] = ("FP64 oracle values written by tests/golden/make_golden.py (oracle/ only) "
+                     "on the seeded inputs of workloads/")
+    t0 = time.time()
+    prob, g, b = W.gnp_n26()
+    e, nrm = oracle.run_expect(prob.n, prob.edges, prob.weights, g, b)
+    out["gnp_n26"] = {"n": prob.n, "num_edges": int(prob.num_edges), "p": len(g), "expect": e, "norm": nrm}
+    print(f"gnp_n26: <C> = {e!r} ({time.time() - t0:.1f} s)", flush=True)
+
+    prob, params = W.grad_gnp_n24()
+    sets = []
+    for i, (g, b) in enumerate(params):
+        e, dg, db = oracle.grad(prob.n, prob.edges, prob.weights, g, b)
+        sets.append({"expect": e, "dgamma": dg.tolist(), "dbeta": db.tolist()})
+        print(f"grad_gnp_n24 set {i}: <C> = {e:.12f} ({time.time() - t0:.1f} s)", flush=True)
+    out["grad_gnp_n24"] = {"n": prob.n, "num_edges": int(prob.num_edges), "p": len(params[0][0]), "sets": sets}
+    json.dump(out, open(OUT, "w"), indent=1)
+
+    if not skip30:
+        prob, g, b = W.weighted_3reg_n30()
+        e, nrm = oracle.run_expect(prob.n, prob.edges, prob.weights, g, b)
+        out["weighted_3reg_n30"] = {"n": prob.n, "num_edges": int(prob.num_edges), "p": len(g), "expect": e,
+                                    "norm": nrm}
+        print(f"weighted_3reg_n30: <C> = {e!r} ({time.time() - t0:.1f} s)", flush=True)
+    json.dump(out, open(OUT, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main()

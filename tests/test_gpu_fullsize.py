@@ -1,0 +1,182 @@
+"""GPU parity at the full workload sizes, with the launch configuration the
+benchmark times (same library calls, same tile plan).
+
+The oracle cannot evolve n = 30 inside a test, so the full-size checks use
+  * stored oracle results (tests/golden/oracle_fullsize.json, written by
+    tests/golden/make_golden.py from oracle/ alone);
+  * results fixed at any size: the p = 1 closed form, the p = 2 light cone
+    (exact oracle simulation of each edge's distance-2 subgraph), norm 1,
+    <C>(gamma, beta) = <C>(-gamma, -beta) = <C>(gamma, beta + pi/2), and
+    <C> = W/2 when all gammas (or all betas) are zero.
+Tolerances as for the small cases: complex128 <C> within 1e-10 |E|,
+complex64 within 1e-4 |E| and 1 - fidelity <= 1e-5.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2312_03019_amd as q  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_fullsize.json")
+
+
+def _golden(key):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("stored oracle values not generated")
+    d = json.load(open(GOLDEN))
+    if key not in d:
+        pytest.skip(f"stored oracle values lack {key}")
+    return d[key]
+
+
+def _tol(prec, m):
+    return (1e-10 if prec == "c128" else 1e-4) * max(1, m)
+
+
+def _expect(prob, prec, g, b):
+    sim = q.Simulator(prob.n, prob.edges, prob.weights, prec)
+    try:
+        return sim.expect(g, b)
+    finally:
+        sim.close()
+
+
+def _zz(ns, se, sw, gamma, beta, a, b):
+    psi = oracle.evolve(ns, se, sw, gamma, beta)
+    z = np.arange(1 << ns)
+    sgn = 1.0 - 2.0 * (((z >> a) ^ (z >> b)) & 1)
+    return float(np.sum(np.abs(psi) ** 2 * sgn))
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_n30_p1_closed_form(prec):
+    prob, g, b = W.weighted_3reg_n30()
+    e, nrm = _expect(prob, prec, g[:1], b[:1])
+    cf = oracle.closed_form_p1(prob.n, prob.edges, prob.weights, g[0], b[0])
+    print(f"n=30 p=1 {prec}: gpu {e!r} closed form {cf!r}")
+    assert abs(e - cf) <= _tol(prec, prob.num_edges)
+    assert abs(nrm - 1) <= (1e-12 if prec == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_n30_p2_light_cone(prec):
+    prob, g, b = W.weighted_3reg_n30()
+    e, _ = _expect(prob, prec, g[:2], b[:2])
+    lc = oracle.light_cone_expect(prob.n, prob.edges, prob.weights, g[:2], b[:2], _zz)
+    print(f"n=30 p=2 {prec}: gpu {e!r} light cone {lc!r}")
+    assert abs(e - lc) <= _tol(prec, prob.num_edges)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_n30_p10_matches_stored_oracle(prec):
+    ref = _golden("weighted_3reg_n30")
+    prob, g, b = W.weighted_3reg_n30()
+    e, nrm = _expect(prob, prec, g, b)
+    print(f"n=30 p=10 {prec}: gpu {e!r} oracle {ref['expect']!r}")
+    assert abs(e - ref["expect"]) <= _tol(prec, prob.num_edges)
+    assert abs(nrm - 1) <= (1e-12 if prec == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_n30_symmetries_and_special_cases(prec):
+    prob, g, b = W.weighted_3reg_n30()
+    m = prob.num_edges
+    g3, b3 = g[:3], b[:3]
+    e0, _ = _expect(prob, prec, g3, b3)
+    e1, _ = _expect(prob, prec, -g3, -b3)                       # complex conjugate state
+    e2, _ = _expect(prob, prec, g3, b3 + math.pi / 2)           # every layer flips all qubits
+    e3, _ = _expect(prob, prec, np.zeros(3), b3)
+    e4, _ = _expect(prob, prec, g3, np.zeros(3))
+    half = float(np.sum(prob.weights)) / 2
+    print(f"n=30 {prec}: {e0!r} {e1!r} {e2!r} {e3!r} {e4!r} W/2={half!r}")
+    for x in (e1, e2):
+        assert abs(x - e0) <= _tol(prec, m)
+    for x in (e3, e4):
+        assert abs(x - half) <= _tol(prec, m)
+
+
+def test_n30_p10_c64_against_c128():
+    prob, g, b = W.weighted_3reg_n30()
+    a = q.Simulator(prob.n, prob.edges, prob.weights, "c64")
+    c = q.Simulator(prob.n, prob.edges, prob.weights, "c128")
+    try:
+        ea, _ = a.expect(g, b)
+        ec, _ = c.expect(g, b)
+        f = a.fidelity(c)
+    finally:
+        a.close()
+        c.close()
+    print(f"n=30 p=10: c64 {ea!r} c128 {ec!r} 1-F {1 - f:.3e}")
+    assert abs(ea - ec) <= 1e-4 * prob.num_edges
+    assert 1 - f <= 1e-5
+
+
+def test_n26_config_both_precisions():
+    ref = _golden("gnp_n26")
+    prob, g, b = W.gnp_n26()
+    a = q.Simulator(prob.n, prob.edges, None, "c64")
+    c = q.Simulator(prob.n, prob.edges, None, "c128")
+    try:
+        ea, na = a.expect(g, b)
+        ec, nc = c.expect(g, b)
+        f = a.fidelity(c)
+    finally:
+        a.close()
+        c.close()
+    print(f"n=26 p=4: c64 {ea!r} c128 {ec!r} oracle {ref['expect']!r} 1-F {1 - f:.3e}")
+    assert abs(ec - ref["expect"]) <= 1e-10 * prob.num_edges
+    assert abs(ea - ref["expect"]) <= 1e-4 * prob.num_edges
+    assert abs(nc - 1) <= 1e-12 and abs(na - 1) <= 1e-5
+    assert 1 - f <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_n24_gradients_all_64_sets(prec):
+    ref = _golden("grad_gnp_n24")
+    prob, params = W.grad_gnp_n24()
+    m = prob.num_edges
+    sim = q.Simulator(prob.n, prob.edges, None, prec)
+    worst = 0.0
+    try:
+        for (g, b), r in zip(params, ref["sets"]):
+            e, dg, db = sim.grad(g, b)
+            err = max(np.max(np.abs(dg - r["dgamma"])), np.max(np.abs(db - r["dbeta"])))
+            worst = max(worst, err)
+            assert abs(e - r["expect"]) <= _tol(prec, m)
+            assert err <= (1e-9 if prec == "c128" else 1e-3) * m
+    finally:
+        sim.close()
+    print(f"n=24 p=8 {prec}: worst gradient error over 64 sets {worst:.3e} (|E| = {m})")
+
+
+def test_n24_gradient_vs_central_differences():
+    prob, params = W.grad_gnp_n24()
+    sim = q.Simulator(prob.n, prob.edges, None, "c128")
+    h = 1e-6
+    try:
+        for g, b in params[:2]:
+            _, dg, db = sim.grad(g, b)
+            for l in range(len(g)):
+                for arr, d in ((g, dg), (b, db)):
+                    a1, a2 = arr.copy(), arr.copy()
+                    a1[l] += h
+                    a2[l] -= h
+                    if arr is g:
+                        fd = (sim.expect(a1, b)[0] - sim.expect(a2, b)[0]) / (2 * h)
+                    else:
+                        fd = (sim.expect(g, a1)[0] - sim.expect(g, a2)[0]) / (2 * h)
+                    assert abs(fd - d[l]) <= 1e-6 * prob.num_edges
+    finally:
+        sim.close()

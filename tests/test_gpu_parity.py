@@ -143,3 +143,48 @@ def test_bound_torch_state_and_stream():
     ref = oracle.evolve(18, pr.edges, None, g, b)
     assert np.max(np.abs(buf.cpu().numpy() - ref)) < 1e-12
     assert abs(e - oracle.run_expect(18, pr.edges, None, g, b)[0]) < 1e-10 * pr.num_edges
+
+
+# A layer with |sin beta| > |cos beta| is applied in its shifted factored form,
+# which leaves every qubit flipped; an odd number of them leaves the stored
+# state complemented (psi(~z) at z).  Readback, bound buffers and overlaps
+# must still see the natural order.
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("n", [9, 14, 17])
+def test_state_after_shifted_angle_layers(prec, n):
+    pr = _prob(90 + n, n, "gnp", True, 0.4)
+    for g, b in (([0.7], [1.2]), ([0.7, 0.3], [1.2, 0.25]), ([0.7, 0.3, 1.1], [1.2, 1.4, 2.0])):
+        sim = q.Simulator(n, pr.edges, pr.weights, prec)
+        sim.run(g, b)
+        psi = sim.state().astype(np.complex128)
+        ref = oracle.evolve(n, pr.edges, pr.weights, g, b)
+        sim.close()
+        assert np.max(np.abs(psi - ref)) < (1e-12 if prec == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_bound_state_after_shifted_angle_layer(prec):
+    n = 16
+    pr = _prob(95, n, "3reg", False)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    buf = torch.empty(1 << n, dtype=dt, device="cuda")
+    sim = q.Simulator(n, pr.edges, None, prec)
+    q.qaoa_bind_state(sim.handle, buf)
+    sim.expect([0.5], [1.3])
+    torch.cuda.synchronize()
+    ref = oracle.evolve(n, pr.edges, None, [0.5], [1.3])
+    assert np.max(np.abs(buf.cpu().numpy().astype(np.complex128) - ref)) < (1e-12 if prec == "c128" else 1e-5)
+
+
+def test_fidelity_between_complemented_and_plain_states():
+    n = 15
+    pr = _prob(96, n, "gnp", False, 0.4)
+    a = q.Simulator(n, pr.edges, None, "c128").run([0.4], [1.2])      # stored complemented
+    b = q.Simulator(n, pr.edges, None, "c128").run([0.9], [0.3])      # natural order
+    c = q.Simulator(n, pr.edges, None, "c64").run([0.4], [1.2])
+    ra = oracle.evolve(n, pr.edges, None, [0.4], [1.2])
+    rb = oracle.evolve(n, pr.edges, None, [0.9], [0.3])
+    ref = oracle.fidelity(n, ra, rb)
+    assert abs(a.fidelity(b) - ref) < 1e-12 and abs(b.fidelity(a) - ref) < 1e-12
+    assert abs(c.fidelity(b) - ref) < 1e-5
+    assert 1 - a.fidelity(c) < 1e-5
