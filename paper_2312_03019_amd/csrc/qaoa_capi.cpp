@@ -184,7 +184,7 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
   const PassDesc* dbwd = (const PassDesc*)(c->dev_img + lay.off_bwd);
   for (size_t i = 0; i < nb; ++i) {
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * (nf + i)], c->stream));
-    HIPCHK(launch_pass(pc.prec, true, logr, 0, dbwd + i, 1, ntiles, nthreads, c->stream));
+    HIPCHK(launch_pass(pc.prec, true, logr, img.bwd[i].shape, dbwd + i, 1, ntiles, nthreads, c->stream));
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * (nf + i) + 1], c->stream));
   }
   HIPCHK(launch_reduce((const ReduceJob*)(c->dev_img + lay.off_jobs), (const Span*)(c->dev_img + lay.off_spans),

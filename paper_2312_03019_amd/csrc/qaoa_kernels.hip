@@ -1,17 +1,18 @@
 // gfx950 kernels of the QAOA max-cut state-vector simulator.
 //
 // Hot path (one launch per HBM pass, see qaoa_plan.h for the tile layout):
-//   k_forward  : load a tile (or synthesise |+>^n, launch control), run the
+//   k_fwd      : load a tile (or synthesise |+>^n, launch control), run the
 //                pass's segments -- each an optional diagonal cost phase
 //                exp(-i gamma C(z)) (rotation compression, Eq. UC_opt /
 //                Algorithm 2, cut counted with Algorithm 3's popcount form
 //                for unweighted graphs) followed by exp(-i beta X_q) on the
 //                pass's qubits -- then optionally accumulate <C> and the norm
 //                in FP64, and store.
-//   k_backward : the adjoint sweep: undo a forward pass on (phi, lam) while
+//   k_bwd      : the adjoint sweep: undo a forward pass on (phi, lam) while
 //                accumulating Im<lam|X_q|phi> and Im<lam|C|phi> in FP64.
-// Support: k_reduce (deterministic second-stage sums), k_cut_table_*,
-// k_overlap (fidelity), k_copy (bandwidth reference).
+// Support: k_tile_cut (per-tile cut values), k_reduce (deterministic
+// second-stage sums), k_cut_table_*, k_overlap (fidelity), k_reverse
+// (complemented state back to natural order), k_copy (bandwidth reference).
 //
 // Design notes.  The state streams through each CU once per pass: every
 // amplitude is read and written exactly once, and all butterflies of the
@@ -239,6 +240,28 @@ __device__ __forceinline__ void rx_round(cx<R> (&v)[1 << LOGR], int mask, R t, i
   }
 }
 
+// The same with a uniform branch per bit instead of t = 0 (the adjoint sweep,
+// whose rounds often hold few mask bits).
+template <typename R, int LOGR>
+__device__ __forceinline__ void rx_round_br(cx<R> (&v)[1 << LOGR], int mask, R t, int cand) {
+#pragma unroll
+  for (int k = 0; k < LOGR; ++k) {
+    if (!(((cand & mask) >> k) & 1)) continue;
+#pragma unroll
+    for (int j = 0; j < (1 << LOGR); ++j) {
+      if (!(j & (1 << k))) {
+        cx<R>& a = v[j];
+        cx<R>& b = v[j | (1 << k)];
+        const cx<R> A = a, B = b;
+        a.re = fma(t, B.im, A.re);
+        a.im = fma(-t, B.re, A.im);
+        b.re = fma(t, A.im, B.re);
+        b.im = fma(-t, A.re, B.im);
+      }
+    }
+  }
+}
+
 template <typename R, int LOGR>
 __device__ __forceinline__ void rx_regs(cx<R> (&v)[1 << LOGR], int mask, R c, R s) {
 #pragma unroll
@@ -404,35 +427,56 @@ __device__ __forceinline__ SiteVals site_values(const QCONST double* __restrict_
 // per-amplitude phase is exp(-i gamma C(z0)) * prod_{k in J} exp(-i gamma d_k)
 // * exp(-i gamma RT[J]); the product over J is split into a low and a high
 // half-tree so only 2^3 + 2^(LOGR-3) partial products stay in registers.
+// `pre` multiplies every factor (a carried scalar).
 template <typename R, int LOGR>
-__device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVals& sv0, double gamma,
+struct PhaseTrees {
+  static constexpr int LO = LOGR < 3 ? LOGR : 3;
+  static constexpr int HI = LOGR - LO;
+  cx<R> lo[1 << LO], hi[1 << HI];
+  __device__ __forceinline__ PhaseTrees(const SiteVals& sv, double gamma, bool undo, cx<R> pre) {
+    const double gs = undo ? -gamma : gamma;
+    lo[0] = cmul(expmi<R>(gs * sv.cz0), pre);
+#pragma unroll
+    for (int k = 0; k < LO; ++k) {
+      const cx<R> e = expmi<R>(gs * sv.d[k]);
+#pragma unroll
+      for (int j = 0; j < (1 << k); ++j) lo[j | (1 << k)] = cmul(lo[j], e);
+    }
+    hi[0] = {(R)1, (R)0};
+#pragma unroll
+    for (int k = 0; k < HI; ++k) {
+      const cx<R> e = expmi<R>(gs * sv.d[LO + k]);
+#pragma unroll
+      for (int j = 0; j < (1 << k); ++j) hi[j | (1 << k)] = cmul(hi[j], e);
+    }
+  }
+  // the factor of register index j
+  __device__ __forceinline__ cx<R> at(int j, cx<R> rt, bool undo) const {
+    const cx<R> t = cmul(lo[j & ((1 << LO) - 1)], hi[j >> LO]);
+    return undo ? cmulc(t, rt) : cmul(t, rt);
+  }
+};
+
+template <typename R, int LOGR>
+__device__ __forceinline__ void apply_phase(cx<R> (&v)[1 << LOGR], const SiteVals& sv, double gamma,
                                             const QCONST cx<R>* __restrict__ rtph, bool undo,
                                             cx<R> pre = {(R)1, (R)0}) {
-  constexpr int LO = LOGR < 3 ? LOGR : 3;
-  constexpr int HI = LOGR - LO;
-  const SiteVals& sv = sv0;
-  const double gs = undo ? -gamma : gamma;
-  cx<R> plo[1 << LO], phi[1 << HI];
-  plo[0] = cmul(expmi<R>(gs * sv.cz0), pre);
+  const PhaseTrees<R, LOGR> T(sv, gamma, undo, pre);
 #pragma unroll
-  for (int k = 0; k < LO; ++k) {
-    const cx<R> e = expmi<R>(gs * sv.d[k]);
-#pragma unroll
-    for (int j = 0; j < (1 << k); ++j) plo[j | (1 << k)] = cmul(plo[j], e);
-  }
-  phi[0] = {(R)1, (R)0};
-#pragma unroll
-  for (int k = 0; k < HI; ++k) {
-    const cx<R> e = expmi<R>(gs * sv.d[LO + k]);
-#pragma unroll
-    for (int j = 0; j < (1 << k); ++j) phi[j | (1 << k)] = cmul(phi[j], e);
-  }
+  for (int j = 0; j < (1 << LOGR); ++j) v[j] = cmul(v[j], T.at(j, rtph[j], undo));
+}
+
+// The same phase on two vectors (the adjoint sweep's phi and lam), factors computed once.
+template <typename R, int LOGR>
+__device__ __forceinline__ void apply_phase2(cx<R> (&f)[1 << LOGR], cx<R> (&l)[1 << LOGR], const SiteVals& sv,
+                                             double gamma, const QCONST cx<R>* __restrict__ rtph, bool undo,
+                                             cx<R> pre) {
+  const PhaseTrees<R, LOGR> T(sv, gamma, undo, pre);
 #pragma unroll
   for (int j = 0; j < (1 << LOGR); ++j) {
-    const cx<R> rt = rtph[j];
-    const cx<R> t = undo ? cmulc(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt)
-                         : cmul(cmul(plo[j & ((1 << LO) - 1)], phi[j >> LO]), rt);
-    v[j] = cmul(v[j], t);
+    const cx<R> t = T.at(j, rtph[j], undo);
+    f[j] = cmul(f[j], t);
+    l[j] = cmul(l[j], t);
   }
 }
 
@@ -578,6 +622,7 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
     double aE = 0.0, aN = 0.0, c = sve.cz0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
+      if (i % 8 == 0) __builtin_amdgcn_sched_barrier(0);   // RT eight entries at a time
       const int J = i ^ (i >> 1);
       if (i > 0) {
         const int k = __builtin_ctz(i);
@@ -605,34 +650,50 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
 // Im sum over register pairs of conj(l_a) f_b + conj(l_b) f_a, for the qubits in mask.
 template <typename R, int LOGR>
 __device__ __forceinline__ double dbeta_round(const cx<R> (&f)[1 << LOGR], const cx<R> (&l)[1 << LOGR],
-                                              int mask) {
+                                              int mask, int cand = (1 << LOGR) - 1) {
+  // Bits outside the mask are skipped by a uniform branch.
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < LOGR; ++k) {
-    if (mask & (1 << k)) {
-      R a = (R)0;
+    if (!(((cand & mask) >> k) & 1)) continue;
+    R a = (R)0;
 #pragma unroll
-      for (int j = 0; j < (1 << LOGR); ++j) {
-        if (!(j & (1 << k))) {
-          const int b = j | (1 << k);
-          a += l[j].re * f[b].im - l[j].im * f[b].re + l[b].re * f[j].im - l[b].im * f[j].re;
-        }
+    for (int j = 0; j < (1 << LOGR); ++j) {
+      if (!(j & (1 << k))) {
+        const int b = j | (1 << k);
+        a = fma(l[j].re, f[b].im, a);
+        a = fma(-l[j].im, f[b].re, a);
+        a = fma(l[b].re, f[j].im, a);
+        a = fma(-l[b].im, f[j].re, a);
       }
-      acc += (double)a;
     }
+    acc += (double)a;
   }
   return acc;
 }
 
-template <typename R, int LOGR, int KB>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) k_backward(const PassDesc* __restrict__ descs, int ndesc) {
+// One pass of the adjoint sweep: undo a forward pass on (phi, lam) while
+// accumulating the dbeta terms Im <lam| X_q |phi> of every mixer qubit (at any
+// point of its layer's undo, since X_q commutes with the layer's other RX) and
+// the dgamma term Im <lam| C |phi> at each cost phase, before undoing it.
+// Template knobs as for k_fwd (0 / -1 = from the descriptor); NOSTORE: the
+// pass that undoes the first forward pass stores nothing.  Rounds of shaped
+// kernels follow the full-width pattern; both vectors move through the full
+// LDS (two workgroups per CU either way, with 2 x 2^LOGR amplitudes per thread).
+template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int NOSTORE>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
   constexpr int NR = 1 << LOGR;
+  constexpr bool SHAPED = NRC > 0;
   __shared__ cx<R> lds[1 << KB];
   __shared__ double red[2 * (kMaxThreads / 64)];
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
   const int64_t g = tile_of_block(D, ndesc);
-  const int L = D.L, h = D.h, nr = D.nrounds, nseg = D.nseg, nth = blockDim.x;
+  const int L = D.L, h = D.h, nth = blockDim.x;
+  const int nr = NRC > 0 ? NRC : D.nrounds;
+  const int nseg = NSC > 0 ? NSC : D.nseg;
+  const bool nostore = NOSTORE >= 0 ? NOSTORE != 0 : (D.flags & PF_NO_STORE) != 0;
   const int64_t nt = D.ntiles;
   const uint64_t zbase = tile_zbase(D, g);
   QGLOBAL cx<R>* __restrict__ phi = gmem<cx<R>>(D.psi);
@@ -640,53 +701,70 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
   QGLOBAL double* __restrict__ part = gmem<double>(D.part);
   const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
   const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
+  const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
+  const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
 
   const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
   cx<R> f[NR], l[NR];
   load_tile<R, LOGR>(f, phi, zt0, D.rb[0], L, h);
   load_tile<R, LOGR>(l, lamp, zt0, D.rb[0], L, h);
 
-  SiteVals sv0{}, sv1{};
-  if (D.flags & (PF_SITE0 | PF_SITE1)) {
-    const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
-    const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
-    if (D.flags & PF_SITE0)
-      sv0 = site_values<LOGR>(dtab, D.site[0], tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
-    if (D.flags & PF_SITE1)
-      sv1 = site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth);
-  }
+  auto has_phase = [&](int s) __attribute__((always_inline)) {
+    return PHM >= 0 ? ((PHM >> s) & 1) != 0 : segs[s].has_phase != 0;
+  };
+  // Site 0 is read with the tile; site 1 (the second segment's phase) where
+  // it is used, which keeps it out of the registers of the rounds before.
+  const bool need0 = PHM >= 0 ? (PHM & 1) != 0 : (D.flags & PF_SITE0) != 0;
+  SiteVals s0{};
+  if (need0) s0 = site_values<LOGR>(dtab, D.site[0], tcrow, tbase<LOGR>(tid, D.rb[0]), D.rb[0], D.K, tid, nth);
 
+  // (lambdas forced inline: an outlined call would move f[], l[] to scratch memory)
+  auto rbase = [&](int i) __attribute__((always_inline)) {
+    return SHAPED ? (KB - LOGR - i * (LOGR - 1) > 0 ? KB - LOGR - i * (LOGR - 1) : 0) : D.rb[i];
+  };
+  auto step = [&](int from, int to) __attribute__((always_inline)) {
+    transpose<R, LOGR>(lds, f, tid, rbase(from), rbase(to));
+    transpose<R, LOGR>(lds, l, tid, rbase(from), rbase(to));
+  };
   int cur = 0;
-  if ((nseg & 1) && nr > 1) {
-    transpose<R, LOGR>(lds, f, tid, D.rb[0], D.rb[nr - 1]);
-    transpose<R, LOGR>(lds, l, tid, D.rb[0], D.rb[nr - 1]);
+  if ((nseg & 1) && nr > 1) {   // the last forward segment ended in the last round
+    step(0, nr - 1);
     cur = nr - 1;
   }
-  for (int s = nseg - 1; s >= 0; --s) {
+#pragma unroll
+  for (int s = (NSC > 0 ? NSC : 64) - 1; s >= 0; --s) {
+    if (NSC <= 0 && s >= nseg) continue;
     const SegDesc sg = segs[s];
-    const R c = (R)sg.cb, sn = (R)(-sg.sb);  // exp(+i beta X) undoes the mixer
+    const R t = (R)sg.bcoef;
     double dB = 0.0;
-    const bool fwd_even = !(s & 1);
-    for (int t = 0; t < nr; ++t) {
-      const int i = fwd_even ? nr - 1 - t : t;
+#pragma unroll
+    for (int u = 0; u < (NRC > 0 ? NRC : kMaxRounds); ++u) {
+      if (NRC <= 0 && u >= nr) break;
+      const int i = (s & 1) ? u : nr - 1 - u;   // forward order reversed
       if (i != cur) {
-        transpose<R, LOGR>(lds, f, tid, D.rb[cur], D.rb[i]);
-        transpose<R, LOGR>(lds, l, tid, D.rb[cur], D.rb[i]);
+        step(cur, i);
         cur = i;
       }
-      dB += dbeta_round<R, LOGR>(f, l, D.rxmask[i]);
-      rx_regs<R, LOGR>(f, D.rxmask[i], c, sn);
-      rx_regs<R, LOGR>(l, D.rxmask[i], c, sn);
+      const int cand = (SHAPED && i > 0) ? ((1 << LOGR) - 1) >> (rbase(i) + LOGR - rbase(i - 1)) : (1 << LOGR) - 1;
+      dB = fma(sg.bw[i], dbeta_round<R, LOGR>(f, l, D.rxmask[i], cand), dB);
+      __builtin_amdgcn_sched_barrier(0);
+      rx_round_br<R, LOGR>(f, D.rxmask[i], t, cand);
+      __builtin_amdgcn_sched_barrier(0);
+      rx_round_br<R, LOGR>(l, D.rxmask[i], t, cand);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    double zero = 0.0;
-    block_reduce2(dB, zero, red, blockDim.x);
-    if (tid == 0) part[(int64_t)(2 * s) * nt + g] = dB;
-    if (sg.has_phase) {
-      const SiteVals& sv = (s & 1) ? sv1 : sv0;
-      const QCONST double* __restrict__ rt = cmem<double>(D.dtab) + D.site[s & 1].rt_off;
-      double dG = 0.0, c0 = sv.cz0;
+    double dG = 0.0;
+    if (has_phase(s)) {
+      const SiteVals sv =
+          (s & 1) ? site_values<LOGR>(dtab, D.site[1], tcrow, tbase<LOGR>(tid, D.rb[nr - 1]), D.rb[nr - 1], D.K, tid, nth)
+                  : s0;
+      const QCONST double* __restrict__ rt = dtab + D.site[s & 1].rt_off;
+      double c0 = sv.cz0;
 #pragma unroll
       for (int ii = 0; ii < NR; ++ii) {
+        // (RT read eight entries at a time: hoisting all of them would push
+        // the uniform values out of scalar registers into vector ones)
+        if (ii % 8 == 0) __builtin_amdgcn_sched_barrier(0);
         const int J = ii ^ (ii >> 1);
         if (ii > 0) {
           const int k = __builtin_ctz(ii);
@@ -695,21 +773,27 @@ __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_e
         const R im = l[J].re * f[J].im - l[J].im * f[J].re;   // Im(conj(l) f)
         dG = fma(c0 + rt[J], (double)im, dG);
       }
-      block_reduce2(dG, zero, red, blockDim.x);
-      if (tid == 0) part[(int64_t)(2 * s + 1) * nt + g] = dG;
-      if (!((D.flags & PF_NO_STORE) && s == 0)) {
-        apply_phase<R, LOGR>(f, sv, sg.gamma, ctab + sg.ph_off, true);
-        apply_phase<R, LOGR>(l, sv, sg.gamma, ctab + sg.ph_off, true);
+      dG *= sg.bwg;
+      if (!(nostore && s == 0)) {
+        __builtin_amdgcn_sched_barrier(0);
+        apply_phase2<R, LOGR>(f, l, sv, sg.gamma, ctab + sg.ph_off, true, cx<R>{(R)sg.bpre_re, (R)sg.bpre_im});
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-  }
-  if (!(D.flags & PF_NO_STORE)) {
-    if (cur != 0) {
-      transpose<R, LOGR>(lds, f, tid, D.rb[cur], D.rb[0]);
-      transpose<R, LOGR>(lds, l, tid, D.rb[cur], D.rb[0]);
+    block_reduce2(dB, dG, red, nth);
+    if (tid == 0) {
+      part[(int64_t)(2 * s) * nt + g] = dB;
+      part[(int64_t)(2 * s + 1) * nt + g] = dG;
     }
-    store_tile<R, LOGR>(f, phi, zt0, D.rb[0], L, h);
-    store_tile<R, LOGR>(l, lamp, zt0, D.rb[0], L, h);
+  }
+  if (!nostore) {
+    if (cur != 0) step(cur, 0);
+    // An opaque copy of the tile base: the store addresses are recomputed
+    // instead of keeping all load addresses of both vectors live meanwhile.
+    uint64_t zs = zt0;
+    asm volatile("" : "+v"(zs));
+    store_tile<R, LOGR>(f, phi, zs, D.rb[0], L, h);
+    store_tile<R, LOGR>(l, lamp, zs, D.rb[0], L, h);
   }
 }
 
@@ -864,8 +948,27 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
   constexpr int LMAX = sizeof(R) == 4 ? kLogRC64 : kLogRC128;
   if (logr < 1 || logr > LMAX) return hipErrorInvalidValue;
   if (backward) {
+    if (logr == LMAX) {
+      switch (shape) {
+#define QAOA_BWD(NRC, CODE, NSC, PHM, NOSTORE)                                                            \
+  case NRC * 8 + CODE:                                                                                    \
+    hipLaunchKernelGGL((k_bwd<R, LMAX, KB, NRC, NSC, PHM, NOSTORE>), grid, block, 0, st, d, ndesc);       \
+    return hipGetLastError();
+#define QAOA_BWD_NR(NRC)                              \
+  QAOA_BWD(NRC, kShapeFirst, 1, 1, 1)                 \
+  QAOA_BWD(NRC, kShapeSingle, 1, 0, 0)                \
+  QAOA_BWD(NRC, kShapeMerged, 2, 2, 0)
+        QAOA_BWD_NR(1)
+        QAOA_BWD_NR(2)
+        QAOA_BWD_NR(3)
+#undef QAOA_BWD_NR
+#undef QAOA_BWD
+        default:
+          break;
+      }
+    }
 #define QAOA_BWD(LR) \
-  if (logr == LR) hipLaunchKernelGGL((k_backward<R, LR, KB>), grid, block, 0, st, d, ndesc);
+  if (logr == LR) hipLaunchKernelGGL((k_bwd<R, LR, KB, 0, 0, -1, -1>), grid, block, 0, st, d, ndesc);
     QAOA_BWD(1)
     QAOA_BWD(2)
     QAOA_BWD(3)

@@ -81,6 +81,18 @@ struct SegDesc {
   int32_t has_phase;
   int32_t ph_off;           // offset (complex elements) into ctab of exp(-i gamma RT[J])
   int32_t pad;
+  // Adjoint sweep.  Undoing the mixer is factored the same way:
+  // exp(+i beta X) = cos(beta) (I + i tan(beta) X), or (i sin(beta)) X (I - i cot(beta) X),
+  // so the kernel applies (I - i bcoef X) and drops the scalar q per qubit
+  // (and the X, a frame flip under which every gradient term is invariant).
+  // With P the product of the scalars dropped so far, the vectors held are
+  // the true ones divided by P: each round's dbeta sum is weighted by |P|^2
+  // at that round (bw, by round index), the dgamma sum by bwg, and P is
+  // folded into the next undone cost phase (bpre) and then reset.
+  double bcoef;
+  double bpre_re, bpre_im;
+  double bw[kMaxRounds];
+  double bwg;
 };
 
 struct PassDesc {

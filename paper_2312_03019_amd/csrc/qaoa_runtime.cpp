@@ -310,6 +310,22 @@ static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const S
   return code ? d.nrounds * 8 + code : 0;
 }
 
+// Backward shapes: the pass undoing the first forward pass (one segment with
+// its phase, nothing stored), a single segment without phase, and a merged
+// pass (phase in the second segment).  Same round condition as forward_shape.
+static int backward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const SegDesc* segs) {
+  if (d.K != pc.kmax || logr != pc.logr_max || d.nrounds < 1 || d.nrounds > 3) return 0;
+  for (int i = 0; i < d.nrounds; ++i)
+    if (d.rb[i] != std::max(0, d.K - logr - i * (logr - 1))) return 0;
+  const bool nost = d.flags & PF_NO_STORE;
+  const bool ph0 = d.nseg >= 1 && segs[0].has_phase, ph1 = d.nseg >= 2 && segs[1].has_phase;
+  int code = 0;
+  if (d.nseg == 1 && ph0 && nost) code = kShapeFirst;
+  else if (d.nseg == 1 && !ph0 && !nost) code = kShapeSingle;
+  else if (d.nseg == 2 && !ph0 && ph1 && !nost) code = kShapeMerged;
+  return code ? d.nrounds * 8 + code : 0;
+}
+
 void build_run(const RunRequest& rq, RunImage* img) {
   const HostGraph& hg = *rq.hg;
   const int n = hg.n;
@@ -337,6 +353,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
   for (int l = 0; l < rq.p; ++l) mode1_layers += fabs(cos(rq.beta[l])) >= fabs(sin(rq.beta[l])) ? 0 : 1;
   int64_t part = 0;
   std::vector<int64_t> bwd_part(sched.size(), 0);
+  std::vector<int> seg_begin(sched.size(), 0);
   int64_t fwd_part = 0;
 
   for (size_t i = 0; i < sched.size(); ++i) {
@@ -360,6 +377,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
     d.site[1] = sites[ps.set][1];
     // segments; seg pointer patched at pack time (stored as index in `segs`)
     const int seg0 = (int)img->segs.size();
+    seg_begin[i] = seg0;
     bool ph_even = false, ph_odd = false;
     int kq = 0;   // mixer qubits of this pass
     for (int r = 0; r < s.nr; ++r) kq += __builtin_popcount(s.rxmask[r]);
@@ -449,6 +467,40 @@ void build_run(const RunRequest& rq, RunImage* img) {
     }
   }
   img->complemented = (mode1_layers & 1) != 0;
+  if (rq.grad) {
+    // Scalars of the factored adjoint sweep (SegDesc): walk the passes and
+    // segments in the order the sweep undoes them, with the rounds of each
+    // segment in reverse forward order.
+    std::complex<double> P(1.0, 0.0);
+    for (int i = (int)sched.size() - 1; i >= 0; --i) {
+      const PassSpec& ps = sched[i];
+      const SetGeom& st = sets[ps.set];
+      for (int k = (int)ps.seg_layer.size() - 1; k >= 0; --k) {
+        SegDesc& sg = img->segs[seg_begin[i] + k];
+        const double cb = sg.cb, sb = sg.sb;
+        std::complex<double> q;
+        if (fabs(cb) >= fabs(sb)) {
+          sg.bcoef = -sb / cb;                          // (I + i tan(beta) X)
+          q = std::complex<double>(cb, 0.0);
+        } else {
+          sg.bcoef = cb / sb;                           // (I - i cot(beta) X), then X
+          q = std::complex<double>(0.0, sb);
+        }
+        for (int u = 0; u < st.nr; ++u) {
+          const int r = (k & 1) ? u : st.nr - 1 - u;
+          sg.bw[r] = std::norm(P);
+          P *= std::pow(q, __builtin_popcount(st.rxmask[r]));
+        }
+        if (ps.seg_phase[k]) {
+          sg.bwg = std::norm(P);
+          sg.bpre_re = P.real();
+          sg.bpre_im = P.imag();
+          P = 1.0;
+        }
+      }
+    }
+    for (PassDesc& b : img->bwd) b.shape = backward_shape(b, pc, logr, img->segs.data() + (intptr_t)b.segs);
+  }
   // backward launches run from the last forward pass to the first
   std::reverse(img->bwd.begin(), img->bwd.end());
   std::reverse(img->bwd_bytes.begin(), img->bwd_bytes.end());

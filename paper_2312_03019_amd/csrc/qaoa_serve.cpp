@@ -286,7 +286,7 @@ int qaoa_server::step_once(uint64_t step) {
     if (r->next >= r->nlaunch) continue;
     const bool bwd = r->next >= r->nf;
     PassDesc d = bwd ? r->img.bwd[r->next - r->nf] : r->img.fwd[r->next];
-    const int shape = bwd ? 0 : d.shape;
+    const int shape = d.shape;
     Group* g = nullptr;
     for (auto& x : groups)
       if (x.bwd == bwd && x.logr == r->logr && x.nthreads == r->nthreads && x.shape == shape) g = &x;
@@ -341,7 +341,7 @@ int qaoa_server::step_once(uint64_t step) {
     if (r->next >= r->nlaunch) continue;
     const bool bwd = r->next >= r->nf;
     PassDesc d = bwd ? r->img.bwd[r->next - r->nf] : r->img.fwd[r->next];
-    const int shape = bwd ? 0 : d.shape;
+    const int shape = d.shape;
     Group* g = nullptr;
     for (auto& x : groups)
       if (x.bwd == bwd && x.logr == r->logr && x.nthreads == r->nthreads && x.shape == shape) g = &x;
