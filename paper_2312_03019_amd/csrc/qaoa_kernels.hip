@@ -202,46 +202,15 @@ __device__ __forceinline__ void transpose_half(cx<R>* lds, cx<R> (&v)[1 << LOGR]
   for (int j = 0; j < (1 << LOGR); ++j) v[j] = w[j];
 }
 
-// exp(-i beta X) on a pair (a, b) = amplitudes differing only in that qubit.
-template <typename R>
-__device__ __forceinline__ void bfly(cx<R>& a, cx<R>& b, R c, R s) {
-  const cx<R> A = a, B = b;
-  a.re = c * A.re + s * B.im;
-  a.im = c * A.im - s * B.re;
-  b.re = c * B.re + s * A.im;
-  b.im = c * B.im - s * A.re;
-}
-
-// Factored forward mixer on the register bits of one round: for every bit in
-// mask, (a, b) -> (a - i t b, b - i t a); the other bits get t = 0, an exact
-// identity, so the code has no data-dependent branches.  The dropped scalar
-// per qubit (cos beta, or -i sin beta when the segment uses the shifted
-// angle) is applied once per segment elsewhere.
-// `cand` (a compile-time constant in the half-tile kernels) lists the bits
-// that can be in the mask at all; the others generate no code.
-template <typename R, int LOGR>
-__device__ __forceinline__ void rx_round(cx<R> (&v)[1 << LOGR], int mask, R t, int cand = (1 << LOGR) - 1) {
-#pragma unroll
-  for (int k = 0; k < LOGR; ++k) {
-    if (!((cand >> k) & 1)) continue;
-    const R tk = ((mask >> k) & 1) ? t : (R)0;
-#pragma unroll
-    for (int j = 0; j < (1 << LOGR); ++j) {
-      if (!(j & (1 << k))) {
-        cx<R>& a = v[j];
-        cx<R>& b = v[j | (1 << k)];
-        const cx<R> A = a, B = b;
-        a.re = fma(tk, B.im, A.re);
-        a.im = fma(-tk, B.re, A.im);
-        b.re = fma(tk, A.im, B.re);
-        b.im = fma(-tk, A.re, B.im);
-      }
-    }
-  }
-}
-
-// The same with a uniform branch per bit instead of t = 0 (the adjoint sweep,
-// whose rounds often hold few mask bits).
+// Factored mixer on the register bits of one round: for every bit in mask,
+// (a, b) -> (a - i t b, b - i t a).  The dropped scalar per qubit (cos beta,
+// or -i sin beta when the segment uses the shifted angle; for the adjoint
+// sweep the corresponding undo scalars) is applied elsewhere.  `cand` (a
+// compile-time constant in the shaped kernels) lists the bits that can be in
+// the mask at all; the others generate no code.  Bits outside the (runtime)
+// mask are skipped by a uniform branch: rounds often hold only a few mask
+// bits, and a branch-free form (t = 0) lets the scheduler overlap every bit's
+// work and run out of registers.
 template <typename R, int LOGR>
 __device__ __forceinline__ void rx_round_br(cx<R> (&v)[1 << LOGR], int mask, R t, int cand) {
 #pragma unroll
@@ -262,17 +231,6 @@ __device__ __forceinline__ void rx_round_br(cx<R> (&v)[1 << LOGR], int mask, R t
   }
 }
 
-template <typename R, int LOGR>
-__device__ __forceinline__ void rx_regs(cx<R> (&v)[1 << LOGR], int mask, R c, R s) {
-#pragma unroll
-  for (int k = 0; k < LOGR; ++k) {
-    if (mask & (1 << k)) {
-#pragma unroll
-      for (int j = 0; j < (1 << LOGR); ++j)
-        if (!(j & (1 << k))) bfly(v[j], v[j | (1 << k)], c, s);
-    }
-  }
-}
 
 // exp(-i th) = cos th - i sin th in the working precision, for the moderate
 // angles the cost phase produces.  Reduction (Cody-Waite): k = rint(th * 2/pi),
@@ -594,7 +552,7 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
       // Half tiles: round i > 0 shares its top bits with round i-1, which
       // mixed them (the masks give each qubit to the first round holding it).
       const int cand = (HALF && i > 0) ? ((1 << LOGR) - 1) >> (rbase(i) + LOGR - rbase(i - 1)) : (1 << LOGR) - 1;
-      rx_round<R, LOGR>(v, D.rxmask[i], t, cand);
+      rx_round_br<R, LOGR>(v, D.rxmask[i], t, cand);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -961,6 +919,7 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
         QAOA_BWD_NR(1)
         QAOA_BWD_NR(2)
         QAOA_BWD_NR(3)
+        QAOA_BWD(4, kShapeSingle, 1, 0, 0)   // the complex128 low set
 #undef QAOA_BWD_NR
 #undef QAOA_BWD
         default:

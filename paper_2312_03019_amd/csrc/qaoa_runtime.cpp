@@ -314,15 +314,15 @@ static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const S
 // its phase, nothing stored), a single segment without phase, and a merged
 // pass (phase in the second segment).  Same round condition as forward_shape.
 static int backward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const SegDesc* segs) {
-  if (d.K != pc.kmax || logr != pc.logr_max || d.nrounds < 1 || d.nrounds > 3) return 0;
+  if (d.K != pc.kmax || logr != pc.logr_max || d.nrounds < 1 || d.nrounds > 4) return 0;
   for (int i = 0; i < d.nrounds; ++i)
     if (d.rb[i] != std::max(0, d.K - logr - i * (logr - 1))) return 0;
   const bool nost = d.flags & PF_NO_STORE;
   const bool ph0 = d.nseg >= 1 && segs[0].has_phase, ph1 = d.nseg >= 2 && segs[1].has_phase;
   int code = 0;
-  if (d.nseg == 1 && ph0 && nost) code = kShapeFirst;
+  if (d.nseg == 1 && ph0 && nost && d.nrounds <= 3) code = kShapeFirst;
   else if (d.nseg == 1 && !ph0 && !nost) code = kShapeSingle;
-  else if (d.nseg == 2 && !ph0 && ph1 && !nost) code = kShapeMerged;
+  else if (d.nseg == 2 && !ph0 && ph1 && !nost && d.nrounds <= 3) code = kShapeMerged;
   return code ? d.nrounds * 8 + code : 0;
 }
 
