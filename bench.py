@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-gates", action="store_true")
     ap.add_argument("--profile-out", default=os.path.join(ROOT, "gpurun_out", "bench_passes.json"))
     return ap.parse_args()
 
@@ -158,6 +159,60 @@ def grad_bench(q, torch, W):
     return out
 
 
+def _time(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def gates_bench(q, torch, W, prob, g, b):
+    """The fused passes against the gate-by-gate circuit (one sweep per gate),
+    complex64: the p-scan of the n=30 workload (times normalised to the gate
+    path at p=1, as the paper's p-level figures do) and one complete graph at
+    the paper's table configuration (K_26, p=5, unweighted)."""
+    out = {}
+    rng = W.SplitMix64(77)
+    gg, bb = W.uniform_angles(20, rng)
+    sim = q.Simulator(prob.n, prob.edges, prob.weights, "c64")
+    t_gate = {p: _time(torch, lambda p=p: (sim.run_gates(gg[:p], bb[:p]), q.qaoa_expect(sim.handle)), 2)
+              for p in (1, 2, 3)}
+    t_fused = {p: _time(torch, lambda p=p: sim.expect(gg[:p], bb[:p]), 3) for p in range(1, 21)}
+    v, _ = sim.max_cut()
+    sim.close()
+    base = t_gate[1]
+    out["p_scan"] = {
+        "workload": f"n={prob.n} weighted 3-regular (seed 3), gamma/beta U[0,pi) (seed 77), complex64",
+        "gate_path_ms": {p: t * 1e3 for p, t in t_gate.items()},
+        "fused_ms": {p: t * 1e3 for p, t in t_fused.items()},
+        "fused_over_gate_p1": {p: t / base for p, t in t_fused.items()},
+        "gate_over_gate_p1": {p: t / base for p, t in t_gate.items()},
+        "max_cut": v,
+    }
+    kn = W.complete(26)
+    gk, bk = W.uniform_angles(5, W.SplitMix64(78))
+    sk = q.Simulator(26, kn, None, "c64")
+    tg = _time(torch, lambda: (sk.run_gates(gk, bk), q.qaoa_expect(sk.handle)), 2)
+    tf = _time(torch, lambda: sk.expect(gk, bk), 5)
+    eg = (sk.run_gates(gk, bk), q.qaoa_expect(sk.handle)[0])[1]
+    ef = sk.expect(gk, bk)[0]
+    sk.close()
+    out["complete_n26_p5"] = {"gate_path_ms": tg * 1e3, "fused_ms": tf * 1e3, "speedup": tg / tf,
+                              "expect_gate": eg, "expect_fused": ef,
+                              "sweeps_gate_path": 26 + 5 * (325 + 26), "passes_fused": sk_passes(q, 26, kn, 5)}
+    return out
+
+
+def sk_passes(q, n, edges, p):
+    s = q.Simulator(n, edges, None, "c64")
+    passes, _ = s.plan(p)
+    s.close()
+    return passes
+
+
 def copy_ceiling(q, torch, nbytes=4 << 30, reps=5):
     """Device-to-device streaming copy with the library's probe kernel (GB/s, read + write)."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -259,6 +314,8 @@ def main():
                         "per_launch_bytes": "2*2^n*8 read+write (write-only 2^n*8 for the first pass)"}
     if not a.no_grad:
         line["grad"] = grad_bench(q, torch, W)
+    if not a.no_gates:
+        line["gates"] = gates_bench(q, torch, W, prob, g, b)
     if not a.no_serve:
         line["serve"] = serve_bench(q, W, a.serve_requests)
     if not a.no_cpu:

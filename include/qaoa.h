@@ -95,6 +95,24 @@ int qaoa_expect(qaoa_ctx *ctx, double *expect_out, double *norm_out);
 int qaoa_grad(qaoa_ctx *ctx, int p, const double *gamma, const double *beta,
               double *expect_out, double *dgamma, double *dbeta);
 
+/* The same evolution as qaoa_run, computed gate by gate as Algorithm 1
+ * (Section 2.1) lays the circuit out: |0>, a Hadamard on every qubit, then
+ * per level one diagonal two-qubit sweep per edge (exp(-i gamma_l w_uv) on the
+ * basis states that cut edge (u, v), i.e. the RZZ gate up to the global phase
+ * the ABI convention drops) and one RX sweep per qubit; every gate is one pass
+ * over the state.  It is the uncompressed reference for the fused passes'
+ * speedup (Tables "cpu"/"gpu" and the p-scan of Section 3.4 compare the
+ * paper's optimisations with such a gate-level simulation).  <C> and the norm
+ * are then computed by a separate sweep, so qaoa_expect, qaoa_get_state and
+ * qaoa_fidelity work as after qaoa_run.  Asynchronous like qaoa_run. */
+int qaoa_run_gates(qaoa_ctx *ctx, int p, const double *gamma, const double *beta);
+
+/* The maximum cut max_z C(z) and the lowest z attaining it (the denominator of
+ * the approximation ratio <C> / max C of Section 3.4), by one device sweep
+ * evaluating C(z) as qaoa_cut_table does (so bit-exact in both cases).
+ * Either output pointer may be NULL, not both.  Synchronises the stream. */
+int qaoa_max_cut(qaoa_ctx *ctx, double *value_out, uint64_t *argmax_out);
+
 /* Cut value C(z) for all 2^n z (the per-state totals of Algorithms 2/3, in the
  * max-cut form).  Unweighted: int32 values (bytes = 4*2^n), exact.
  * Weighted: double values (bytes = 8*2^n).  host_out is host memory. */

@@ -70,6 +70,8 @@ _SIGS = {
     "qaoa_run": (_I, [_P, _I, _DP, _DP]),
     "qaoa_expect": (_I, [_P, _DP, _DP]),
     "qaoa_grad": (_I, [_P, _I, _DP, _DP, _DP, _DP, _DP]),
+    "qaoa_run_gates": (_I, [_P, _I, _DP, _DP]),
+    "qaoa_max_cut": (_I, [_P, _DP, ctypes.POINTER(ctypes.c_uint64)]),
     "qaoa_cut_table": (_I, [_P, _P, _SZ]),
     "qaoa_get_state": (_I, [_P, _P, _SZ]),
     "qaoa_fidelity": (_I, [_P, _P, _DP]),
@@ -158,6 +160,19 @@ def qaoa_run(ctx, gamma, beta) -> None:
     if g.shape != b.shape:
         raise QAOAError(QAOA_EINVAL, "gamma and beta differ in length")
     _err(_lib.qaoa_run(ctx, int(g.shape[0]), _dptr(g), _dptr(b)))
+
+
+def qaoa_run_gates(ctx, gamma, beta) -> None:
+    g, b = _f64(gamma), _f64(beta)
+    if g.shape != b.shape:
+        raise QAOAError(QAOA_EINVAL, "gamma and beta differ in length")
+    _err(_lib.qaoa_run_gates(ctx, int(g.shape[0]), _dptr(g), _dptr(b)))
+
+
+def qaoa_max_cut(ctx):
+    v, z = ctypes.c_double(), ctypes.c_uint64()
+    _err(_lib.qaoa_max_cut(ctx, ctypes.byref(v), ctypes.byref(z)))
+    return v.value, int(z.value)
 
 
 def qaoa_expect(ctx):
@@ -287,6 +302,15 @@ class Simulator:
 
     def grad(self, gamma, beta):
         return qaoa_grad(self._h, gamma, beta)
+
+    def run_gates(self, gamma, beta):
+        """The same evolution gate by gate (one sweep per gate), as the uncompressed reference."""
+        qaoa_run_gates(self._h, gamma, beta)
+        return self
+
+    def max_cut(self):
+        """(max_z C(z), lowest z attaining it)."""
+        return qaoa_max_cut(self._h)
 
     def cut_table(self):
         return qaoa_cut_table(self._h, self.n, self.weights is not None)

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqaoa.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["qaoa_kernels.hip", "qaoa_runtime.cpp", "qaoa_capi.cpp", "qaoa_serve.cpp"]
+SOURCES = ["qaoa_kernels.hip", "qaoa_gates.hip", "qaoa_runtime.cpp", "qaoa_capi.cpp", "qaoa_serve.cpp"]
 ARCH = os.environ.get("QAOA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

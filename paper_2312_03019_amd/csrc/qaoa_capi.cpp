@@ -289,6 +289,69 @@ int qaoa_expect(qaoa_ctx* c, double* expect_out, double* norm_out) {
   return QAOA_OK;
 }
 
+int qaoa_run_gates(qaoa_ctx* c, int p, const double* gamma, const double* beta) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  int rc = check_angles(p, gamma, beta);
+  if (rc) return rc;
+  if ((rc = ensure_device(c))) return rc;
+  c->have_state = c->have_expect = false;
+  if (c->upload_pending) {   // the host image buffers are reused below
+    HIPCHK(hipEventSynchronize(c->upload_done));
+    c->upload_pending = false;
+  }
+  const int nb = gate_reduce_blocks(c->hg.n);
+  if ((rc = grow_device((void**)&c->dev_part, &c->dev_part_cap, 2 * nb * sizeof(double), c->stream))) return rc;
+  if ((rc = grow_device((void**)&c->dev_out, &c->dev_out_cap, 2 * sizeof(double), c->stream))) return rc;
+  if ((rc = grow_host((void**)&c->host_out, &c->host_out_cap, 2 * sizeof(double), c))) return rc;
+  GateRun r{c->hg.n, c->hg.m(), p, c->hg.eu.data(), c->hg.ev.data(), c->hg.weighted() ? c->hg.w.data() : nullptr,
+            gamma, beta, c->psi};
+  HIPCHK(launch_gate_run(c->prec == QAOA_C64 ? 1 : 0, r, c->stream));
+  HIPCHK(launch_expect_state(c->prec == QAOA_C64 ? 1 : 0, (const GraphDev*)c->dgraph, c->psi, c->hg.n, c->dev_part,
+                             c->dev_out, c->stream));
+  HIPCHK(hipMemcpyAsync(c->host_out, c->dev_out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  c->complemented = false;
+  c->ntimed = 0;
+  c->have_state = c->have_expect = true;
+  return QAOA_OK;
+}
+
+int qaoa_max_cut(qaoa_ctx* c, double* value_out, uint64_t* argmax_out) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  if (!value_out && !argmax_out) {
+    set_error("value_out and argmax_out are NULL");
+    return QAOA_EINVAL;
+  }
+  int rc = ensure_device(c);
+  if (rc) return rc;
+  const int nb = gate_reduce_blocks(c->hg.n);
+  char* tmp = nullptr;
+  const size_t bytes = (size_t)nb * 16 + 16;
+  HIPCHK(hipMalloc((void**)&tmp, bytes));
+  double* pv = (double*)tmp;
+  uint64_t* pz = (uint64_t*)(tmp + (size_t)nb * 8);
+  double* ov = (double*)(tmp + (size_t)nb * 16);
+  uint64_t* oz = (uint64_t*)(tmp + (size_t)nb * 16 + 8);
+  hipError_t e = launch_max_cut((const GraphDev*)c->dgraph, c->hg.n, pv, pz, ov, oz, c->stream);
+  double v = 0.0;
+  uint64_t z = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&v, ov, 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&z, oz, 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(tmp);
+  HIPCHK(e);
+  if (value_out) *value_out = v;
+  if (argmax_out) *argmax_out = z;
+  return QAOA_OK;
+}
+
 int qaoa_grad(qaoa_ctx* c, int p, const double* gamma, const double* beta, double* expect_out, double* dgamma,
               double* dbeta) {
   Busy b(c);

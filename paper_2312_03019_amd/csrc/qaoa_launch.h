@@ -40,4 +40,23 @@ hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
 // Per-tile cut table (kTileCutStride doubles per tile) of one qubit set.
 hipError_t launch_tile_cut(const GraphDev* g, int K, int L, int h, int64_t ntiles, double* out, hipStream_t st);
 
+// Gate-by-gate circuit (Algorithm 1): |0> -> H on every qubit -> per level one
+// diagonal sweep per edge and one RX sweep per qubit.  Host arrays, canonical
+// edge order; weights may be NULL (all 1).
+struct GateRun {
+  int n, m, p;
+  const int32_t *eu, *ev;
+  const double *weights, *gamma, *beta;
+  void* psi;
+};
+hipError_t launch_gate_run(int prec, const GateRun& r, hipStream_t st);
+// Blocks of the full-state reductions below (part needs 2 doubles per block).
+int gate_reduce_blocks(int n);
+// out[0] = sum |psi|^2 C(z), out[1] = sum |psi|^2, FP64, fixed order.
+hipError_t launch_expect_state(int prec, const GraphDev* g, const void* psi, int n, double* part, double* out,
+                               hipStream_t st);
+// Maximum cut value and its lowest index (pv / pz: one entry per block).
+hipError_t launch_max_cut(const GraphDev* g, int n, double* pv, uint64_t* pz, double* ov, uint64_t* oz,
+                          hipStream_t st);
+
 }  // namespace qaoa

@@ -4,11 +4,12 @@ inside the GPU tests).  Every value comes from oracle/ alone, on the seeded
 inputs of workloads/:
 
   gnp_n26          G(26, 0.5) unweighted, p = 4: <C> and the norm
-  weighted_3reg_n30  random 3-regular, U[0,1) weights, n = 30, p = 10: <C>, norm
+  weighted_3reg_n30  random 3-regular, U[0,1) weights, n = 30, p = 10: <C>, norm,
+                   and its maximum cut (value, lowest maximising z)
   grad_gnp_n24     G(24, 0.3) unweighted, p = 8, 64 parameter sets: <C> and
                    the adjoint gradient (16 values) of every set
 
-Usage: python tests/golden/make_golden.py [--skip-n30]   (n = 30 needs ~24 GiB RAM)
+Usage: python tests/golden/make_golden.py [--skip-n30] [--only-max-cut]   (n = 30 needs ~24 GiB RAM)
 """
 from __future__ import annotations
 
@@ -30,6 +31,14 @@ OUT = os.path.join(HERE, "oracle_fullsize.json")
 def main():
     skip30 = "--skip-n30" in sys.argv
     out = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    if "--only-max-cut" in sys.argv:
+        prob, _, _ = W.weighted_3reg_n30()
+        ct = oracle.cut_table(prob.n, prob.edges, prob.weights)
+        z = int(ct.argmax())
+        out["weighted_3reg_n30_max_cut"] = {"value": float(ct[z]), "argmax": z}
+        json.dump(out, open(OUT, "w"), indent=1)
+        print(out["weighted_3reg_n30_max_cut"])
+        return
     out["_about"] = ("FP64 oracle values written by tests/golden/make_golden.py (oracle/ only) "
                      "on the seeded inputs of workloads/")
     t0 = time.time()
@@ -53,6 +62,11 @@ def main():
         out["weighted_3reg_n30"] = {"n": prob.n, "num_edges": int(prob.num_edges), "p": len(g), "expect": e,
                                     "norm": nrm}
         print(f"weighted_3reg_n30: <C> = {e!r} ({time.time() - t0:.1f} s)", flush=True)
+        ct = oracle.cut_table(prob.n, prob.edges, prob.weights)
+        z = int(ct.argmax())                      # lowest index of the maximum
+        out["weighted_3reg_n30_max_cut"] = {"value": float(ct[z]), "argmax": z}
+        del ct
+        print(f"weighted_3reg_n30 max cut: {out['weighted_3reg_n30_max_cut']} ({time.time() - t0:.1f} s)", flush=True)
     json.dump(out, open(OUT, "w"), indent=1)
 
 
