@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-gates", action="store_true")
+    ap.add_argument("--no-optimize", action="store_true")
     ap.add_argument("--profile-out", default=os.path.join(ROOT, "gpurun_out", "bench_passes.json"))
     return ap.parse_args()
 
@@ -206,6 +207,21 @@ def gates_bench(q, torch, W, prob, g, b):
     return out
 
 
+def optimize_bench(q, W):
+    """Approximation ratio <C>*/max C of optimised angles vs p (Adam over the
+    adjoint gradient, 8 starts batched through the server), n=20 3-regular."""
+    from paper_2312_03019_amd import optimize as opt
+    e = W.random_regular(20, 3, W.SplitMix64(79))
+    out = {"workload": "n=20 random 3-regular unweighted (seed 79), Adam lr 0.04, 8 starts x 100 steps, complex64"}
+    for p in (1, 2, 3, 4, 5):
+        t0 = time.perf_counter()
+        r = opt.optimize(q, 20, e, None, p=p, starts=8, steps=100, lr=0.04, seed=p)
+        out[p] = {"expect": r.expect, "ratio": r.ratio, "seconds": time.perf_counter() - t0,
+                  "gamma": r.gamma.tolist(), "beta": r.beta.tolist()}
+    out["max_cut"] = r.max_cut
+    return out
+
+
 def sk_passes(q, n, edges, p):
     s = q.Simulator(n, edges, None, "c64")
     passes, _ = s.plan(p)
@@ -316,6 +332,8 @@ def main():
         line["grad"] = grad_bench(q, torch, W)
     if not a.no_gates:
         line["gates"] = gates_bench(q, torch, W, prob, g, b)
+    if not a.no_optimize:
+        line["optimize"] = optimize_bench(q, W)
     if not a.no_serve:
         line["serve"] = serve_bench(q, W, a.serve_requests)
     if not a.no_cpu:
