@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-gates", action="store_true")
     ap.add_argument("--no-optimize", action="store_true")
+    ap.add_argument("--no-sample", action="store_true")
     ap.add_argument("--profile-out", default=os.path.join(ROOT, "gpurun_out", "bench_passes.json"))
     return ap.parse_args()
 
@@ -222,6 +223,32 @@ def optimize_bench(q, W):
     return out
 
 
+def sample_bench(q, torch, W, prob, g, b, count=1 << 20):
+    """Bitstrings from |psi|^2 of the n=30 workload's final state: 2^20 samples
+    (inverse CDF: one FP64 pass over the state for chunk sums, then one wave per
+    sample), and the best cut among them against the maximum cut."""
+    sim = q.Simulator(prob.n, prob.edges, prob.weights, "c64")
+    rng = np.random.default_rng(80)
+    u = rng.random(count)
+    try:
+        sim.run(g, b)
+        sim.sample(u[:1024])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        z = sim.sample(u)
+        t = time.perf_counter() - t0
+        mc, _ = sim.max_cut()
+    finally:
+        sim.close()
+    z = z.astype(np.int64)
+    cut = np.zeros(count)
+    for (uu, vv), w in zip(prob.edges, prob.weights):
+        cut += w * (((z >> int(uu)) ^ (z >> int(vv))) & 1)
+    return {"samples": count, "seconds": t, "samples_per_s": count / t, "best_sampled_cut": float(cut.max()),
+            "mean_sampled_cut": float(cut.mean()), "max_cut": mc,
+            "note": "uniforms from numpy default_rng(80); time includes the CDF pass over the 8 GiB state"}
+
+
 def sk_passes(q, n, edges, p):
     s = q.Simulator(n, edges, None, "c64")
     passes, _ = s.plan(p)
@@ -334,6 +361,8 @@ def main():
         line["gates"] = gates_bench(q, torch, W, prob, g, b)
     if not a.no_optimize:
         line["optimize"] = optimize_bench(q, W)
+    if not a.no_sample:
+        line["sample"] = sample_bench(q, torch, W, prob, g, b)
     if not a.no_serve:
         line["serve"] = serve_bench(q, W, a.serve_requests)
     if not a.no_cpu:

@@ -113,6 +113,15 @@ int qaoa_run_gates(qaoa_ctx *ctx, int p, const double *gamma, const double *beta
  * Either output pointer may be NULL, not both.  Synchronises the stream. */
 int qaoa_max_cut(qaoa_ctx *ctx, double *value_out, uint64_t *argmax_out);
 
+/* Draw count bitstrings z from |psi_z|^2 of the last run's state (the
+ * solutions a QAOA run hands to the classical side, Section 1's workflow):
+ * sample k is the smallest z with CDF(z) > uniforms[k] * sum|psi|^2, the CDF
+ * taken over z in natural order in FP64 (so the result is a deterministic
+ * function of the caller's uniforms, each in [0, 1), else QAOA_EINVAL).
+ * uniforms and out are host arrays of count entries.  QAOA_ESTATE without a
+ * state (no run yet, or after qaoa_grad).  Synchronises the stream. */
+int qaoa_sample(qaoa_ctx *ctx, int64_t count, const double *uniforms, uint64_t *out);
+
 /* Cut value C(z) for all 2^n z (the per-state totals of Algorithms 2/3, in the
  * max-cut form).  Unweighted: int32 values (bytes = 4*2^n), exact.
  * Weighted: double values (bytes = 8*2^n).  host_out is host memory. */

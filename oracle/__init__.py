@@ -180,6 +180,24 @@ def fidelity(n, a, b) -> float:
     return f.value
 
 
+def sample_cdf(psi) -> np.ndarray:
+    """CDF(z) = sum_{y <= z} |psi_y|^2 over the natural index order, FP64, added
+    left to right."""
+    p = np.abs(np.asarray(psi, dtype=np.complex128)) ** 2
+    return np.cumsum(p)
+
+
+def sample(psi, uniforms) -> np.ndarray:
+    """Measurement of the final state in the computational basis (the bitstrings
+    a QAOA run hands to the classical side, Section 1's workflow), by inverse
+    CDF: sample k is the smallest z with CDF(z) > u_k * CDF(N-1); the uniforms
+    u_k in [0, 1) are inputs."""
+    c = sample_cdf(psi)
+    t = np.asarray(uniforms, dtype=np.float64) * c[-1]
+    z = np.searchsorted(c, t, side="right")
+    return np.minimum(z, len(c) - 1).astype(np.uint64)
+
+
 def num_threads() -> int:
     return int(load().oracle_num_threads())
 

@@ -72,6 +72,7 @@ _SIGS = {
     "qaoa_grad": (_I, [_P, _I, _DP, _DP, _DP, _DP, _DP]),
     "qaoa_run_gates": (_I, [_P, _I, _DP, _DP]),
     "qaoa_max_cut": (_I, [_P, _DP, ctypes.POINTER(ctypes.c_uint64)]),
+    "qaoa_sample": (_I, [_P, ctypes.c_int64, _DP, ctypes.POINTER(ctypes.c_uint64)]),
     "qaoa_cut_table": (_I, [_P, _P, _SZ]),
     "qaoa_get_state": (_I, [_P, _P, _SZ]),
     "qaoa_fidelity": (_I, [_P, _P, _DP]),
@@ -173,6 +174,13 @@ def qaoa_max_cut(ctx):
     v, z = ctypes.c_double(), ctypes.c_uint64()
     _err(_lib.qaoa_max_cut(ctx, ctypes.byref(v), ctypes.byref(z)))
     return v.value, int(z.value)
+
+
+def qaoa_sample(ctx, uniforms) -> np.ndarray:
+    u = _f64(uniforms).reshape(-1)
+    out = np.zeros(u.shape[0], dtype=np.uint64)
+    _err(_lib.qaoa_sample(ctx, int(u.shape[0]), _dptr(u), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return out
 
 
 def qaoa_expect(ctx):
@@ -307,6 +315,10 @@ class Simulator:
         """The same evolution gate by gate (one sweep per gate), as the uncompressed reference."""
         qaoa_run_gates(self._h, gamma, beta)
         return self
+
+    def sample(self, uniforms):
+        """Bitstrings from |psi|^2 of the last run, one per uniform in [0, 1) (inverse CDF)."""
+        return qaoa_sample(self._h, uniforms)
 
     def max_cut(self):
         """(max_z C(z), lowest z attaining it)."""

@@ -319,6 +319,46 @@ int qaoa_run_gates(qaoa_ctx* c, int p, const double* gamma, const double* beta) 
   return QAOA_OK;
 }
 
+int qaoa_sample(qaoa_ctx* c, int64_t count, const double* uniforms, uint64_t* out) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  if (count < 0 || count > (int64_t(1) << 31) || (count > 0 && (!uniforms || !out))) {
+    set_error("invalid sample count or NULL arrays");
+    return QAOA_EINVAL;
+  }
+  for (int64_t k = 0; k < count; ++k)
+    if (!(uniforms[k] >= 0.0 && uniforms[k] < 1.0)) {
+      set_error("uniform %lld is not in [0, 1)", (long long)k);
+      return QAOA_EINVAL;
+    }
+  if (!c->have_state) {
+    set_error("no state to sample");
+    return QAOA_ESTATE;
+  }
+  const int n = c->hg.n;
+  const int64_t nc = sample_chunks(n);
+  const size_t bytes = (size_t)(2 * nc + 1) * 8 + (size_t)count * 16;
+  char* tmp = nullptr;
+  HIPCHK(hipMalloc((void**)&tmp, bytes));
+  double* sums = (double*)tmp;
+  double* prefix = sums + nc;
+  double* du = prefix + nc + 1;
+  uint64_t* dout = (uint64_t*)(du + count);
+  hipError_t e = hipSuccess;
+  if (count > 0) e = hipMemcpyAsync(du, uniforms, (size_t)count * 8, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = launch_sample(c->prec == QAOA_C64 ? 1 : 0, c->psi, n, c->complemented ? 1 : 0, sums, prefix, du, count, dout,
+                      c->stream);
+  if (e == hipSuccess && count > 0) e = hipMemcpyAsync(out, dout, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(tmp);
+  HIPCHK(e);
+  return QAOA_OK;
+}
+
 int qaoa_max_cut(qaoa_ctx* c, double* value_out, uint64_t* argmax_out) {
   Busy b(c);
   if (!b.ok) {

@@ -1,7 +1,8 @@
 // The uncompressed gate-by-gate circuit (Algorithm 1) on the same state
 // layout, as the reference the fused passes are measured against, plus the
-// two full-state reductions that go with it: <C> of a given state, and the
-// maximum cut max_z C(z) (the denominator of the approximation ratio).
+// full-state sweeps that go with the QAOA loop: <C> of a given state, the
+// maximum cut max_z C(z) (the denominator of the approximation ratio), and
+// sampling bitstrings from |psi|^2 (the solutions a QAOA run hands back).
 //
 // Every gate is one sweep over the state (read + write of 2^n amplitudes):
 // n Hadamards, then per level one diagonal sweep per edge (the RZZ gate of
@@ -214,6 +215,128 @@ __global__ void __launch_bounds__(64) k_max_final(const double* __restrict__ pv,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sampling z with probability |psi_z|^2 / sum |psi|^2 by inverse CDF over the
+// natural index order: sample = min{z : CDF(z) > u * total}, for uniforms u in
+// [0, 1) supplied by the caller.  `rev` reads a complemented state (stored at
+// N-1-z).  Chunks of kChunk amplitudes: per-chunk sums (fixed order), their
+// exclusive prefix (one workgroup, fixed order), then one wave per sample:
+// binary search over the chunk prefix, lane sums of 64 amplitudes each, a
+// wave prefix, and a scan of the one lane that holds the target.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 4096;
+
+template <typename R>
+__device__ __forceinline__ double prob_at(const typename V2<R>::T* psi, int64_t N, int rev, int64_t z) {
+  const typename V2<R>::T a = psi[rev ? N - 1 - z : z];
+  return (double)a.x * a.x + (double)a.y * a.y;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_chunk_sums(const typename V2<R>::T* __restrict__ psi, int64_t N, int rev,
+                                                    double* __restrict__ sums) {
+  __shared__ double red[256];
+  const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+  const int64_t len = N - c0 < kChunk ? N - c0 : kChunk;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += 256) s += prob_at<R>(psi, N, rev, c0 + i);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+// Exclusive prefix of sums[0..nc) into prefix[0..nc], prefix[nc] = total.
+// One workgroup of 1024: each thread scans a contiguous segment in order.
+__global__ void __launch_bounds__(1024) k_scan_chunks(const double* __restrict__ sums, int64_t nc,
+                                                      double* __restrict__ prefix) {
+  __shared__ double seg[1024];
+  const int64_t per = (nc + 1023) / 1024;
+  const int64_t b = (int64_t)threadIdx.x * per;
+  const int64_t e = b + per < nc ? b + per : nc;
+  double s = 0.0;
+  for (int64_t i = b; i < e; ++i) s += sums[i];
+  seg[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int i = 0; i < 1024; ++i) {
+      const double x = seg[i];
+      seg[i] = run;
+      run += x;
+    }
+    prefix[nc] = run;
+  }
+  __syncthreads();
+  double run = seg[threadIdx.x];
+  for (int64_t i = b; i < e; ++i) {
+    prefix[i] = run;
+    run += sums[i];
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_sample(const typename V2<R>::T* __restrict__ psi, int64_t N, int rev,
+                                                const double* __restrict__ prefix, int64_t nc,
+                                                const double* __restrict__ u, int64_t count,
+                                                uint64_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per sample
+  if (k >= count) return;
+  // (kept below the total, so trailing chunks without mass are never chosen)
+  const double total = prefix[nc];
+  double t = u[k] * total;
+  if (t >= total) t = nextafter(total, 0.0);
+  // last chunk c with prefix[c] <= t (prefix is non-decreasing, prefix[0] = 0)
+  int64_t lo = 0, hi = nc - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t c0 = lo * kChunk;
+  const int64_t len = N - c0 < kChunk ? N - c0 : kChunk;
+  const int per = kChunk / 64;
+  double ls = 0.0;
+  for (int i = 0; i < per; ++i) {
+    const int64_t j = (int64_t)lane * per + i;
+    if (j < len) ls += prob_at<R>(psi, N, rev, c0 + j);
+  }
+  double incl = ls;   // inclusive wave prefix of the lane sums
+  for (int off = 1; off < 64; off <<= 1) {
+    const double y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  const double tl = t - prefix[lo];
+  // The first lane whose inclusive sum exceeds the target holds the sample.
+  // If rounding (these sums are re-added in another order than the chunk
+  // sums) leaves no such lane, the sample is the chunk's last element with
+  // nonzero probability, found in the highest lane with mass.
+  const unsigned long long ball = __ballot(incl > tl);
+  const bool found = ball != 0ull;
+  const unsigned long long mass = __ballot(ls > 0.0);
+  const int L = found ? __ffsll(ball) - 1 : (mass ? 63 - __clzll(mass) : 0);
+  if (lane == L) {
+    double run = incl - ls;
+    int64_t last = -1;   // last index with nonzero probability seen so far
+    for (int i = 0; i < per; ++i) {
+      const int64_t j = (int64_t)L * per + i;
+      if (j >= len) break;
+      const double pz = prob_at<R>(psi, N, rev, c0 + j);
+      if (pz > 0.0) last = c0 + j;
+      run += pz;
+      if (found && run > tl) {
+        last = c0 + j;
+        break;
+      }
+    }
+    out[k] = (uint64_t)(last >= 0 ? last : c0);
+  }
+}
+
 template <typename R>
 hipError_t gate_run_t(const GateRun& r, hipStream_t st) {
   typedef typename V2<R>::T T;
@@ -257,6 +380,30 @@ hipError_t launch_expect_state(int prec, const GraphDev* g, const void* psi, int
   else
     hipLaunchKernelGGL(k_expect_state<double>, dim3(nb), dim3(256), 0, st, g, (const V2<double>::T*)psi, N, part);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, part, nb, 2, out);
+  return hipGetLastError();
+}
+
+int64_t sample_chunks(int n) { return ((int64_t(1) << n) + kChunk - 1) / kChunk; }
+
+hipError_t launch_sample(int prec, const void* psi, int n, int rev, double* sums, double* prefix, const double* u,
+                         int64_t count, uint64_t* out, hipStream_t st) {
+  const int64_t N = int64_t(1) << n, nc = sample_chunks(n);
+  if (prec == 1)
+    hipLaunchKernelGGL(k_chunk_sums<float>, dim3((unsigned)nc), dim3(256), 0, st, (const V2<float>::T*)psi, N, rev,
+                       sums);
+  else
+    hipLaunchKernelGGL(k_chunk_sums<double>, dim3((unsigned)nc), dim3(256), 0, st, (const V2<double>::T*)psi, N,
+                       rev, sums);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, st, sums, nc, prefix);
+  if (count > 0) {
+    const dim3 grid((unsigned)((count + 3) / 4));
+    if (prec == 1)
+      hipLaunchKernelGGL(k_sample<float>, grid, dim3(256), 0, st, (const V2<float>::T*)psi, N, rev, prefix, nc, u,
+                         count, out);
+    else
+      hipLaunchKernelGGL(k_sample<double>, grid, dim3(256), 0, st, (const V2<double>::T*)psi, N, rev, prefix, nc, u,
+                         count, out);
+  }
   return hipGetLastError();
 }
 

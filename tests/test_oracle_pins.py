@@ -348,3 +348,37 @@ def test_planted_mistakes_are_caught(tmp_path, name, old, new):
     subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
                     str(mut), "-o", so, "-lm"], check=True, capture_output=True)
     assert _battery(oracle.load(so)) != [], f"planted mistake '{name}' not detected"
+
+
+# --- sampling (inverse CDF) -------------------------------------------------
+def test_sampling_distributions_with_known_cdf():
+    # a basis state is always measured as itself
+    psi = np.zeros(16, complex)
+    psi[11] = 1j
+    assert np.all(oracle.sample(psi, [0.0, 0.3, 0.999999]) == 11)
+    # p = (1/4, 1/4, 1/2, 0): boundaries at 1/4 and 1/2, the zero-probability state never drawn
+    psi = np.sqrt(np.array([0.25, 0.25, 0.5, 0.0])).astype(complex)
+    u = [0.0, 0.24, 0.25, 0.49, 0.5, 0.75, 0.999999]
+    assert oracle.sample(psi, u).tolist() == [0, 0, 1, 1, 2, 2, 2]
+    # uniform state: u in the middle of cell k gives k
+    psi = np.full(8, 8 ** -0.5, complex)
+    assert oracle.sample(psi, [(k + 0.5) / 8 for k in range(8)]).tolist() == list(range(8))
+    # unnormalised input: the CDF is scaled by the total
+    assert oracle.sample(3.0 * np.sqrt(np.array([0.25, 0.75])), [0.2, 0.3]).tolist() == [0, 1]
+
+
+def test_sampling_frequencies_match_probabilities():
+    pr = _rand_problem(95, 6, "gnp", True)
+    g, b = W.uniform_angles(2, W.SplitMix64(96))
+    psi = oracle.evolve(6, pr.edges, pr.weights, g, b)
+    rng = W.SplitMix64(97)
+    u = np.array([rng.u01() for _ in range(40000)])
+    z = oracle.sample(psi, u)
+    counts = np.bincount(z.astype(np.int64), minlength=64)
+    p = np.abs(psi) ** 2
+    from scipy.stats import chisquare
+    keep = p * len(u) >= 5
+    exp = p[keep] * len(u)
+    obs = counts[keep].astype(float)
+    exp *= obs.sum() / exp.sum()
+    assert chisquare(obs, exp).pvalue > 1e-4
