@@ -180,3 +180,38 @@ def test_n24_gradient_vs_central_differences():
                     assert abs(fd - d[l]) <= 1e-6 * prob.num_edges
     finally:
         sim.close()
+
+
+@pytest.mark.parametrize("prec,n", [("c64", 32), ("c128", 31)])
+def test_beyond_2_31_amplitudes_p1_closed_form(prec, n):
+    """32 GiB states: tile indices and byte offsets beyond 32 bits."""
+    if q.qaoa_max_qubits(prec) < n:
+        pytest.skip("not enough free device memory")
+    # 3-regular on an even vertex count (odd n: one isolated vertex more)
+    base = W.random_problem(n - (n & 1), W.SplitMix64(900 + n), "3reg", True)
+    pr = W.Problem(n, base.edges, base.weights, f"w3reg{n - (n & 1)}+{n & 1}")
+    g, b = W.uniform_angles(2, W.SplitMix64(901 + n))
+    e1, nrm = _expect(pr, prec, g[:1], b[:1])
+    cf = oracle.closed_form_p1(n, pr.edges, pr.weights, g[0], b[0])
+    print(f"n={n} {prec} p=1: gpu {e1!r} closed form {cf!r}")
+    assert abs(e1 - cf) <= _tol(prec, pr.num_edges)
+    assert abs(nrm - 1) <= (1e-12 if prec == "c128" else 1e-5)
+    e2, _ = _expect(pr, prec, g, b)
+    lc = oracle.light_cone_expect(n, pr.edges, pr.weights, g, b, _zz)
+    print(f"n={n} {prec} p=2: gpu {e2!r} light cone {lc!r}")
+    assert abs(e2 - lc) <= _tol(prec, pr.num_edges)
+
+
+def test_max_cut_n32_is_a_valid_maximum():
+    n = 32
+    if q.qaoa_max_qubits("c64") < n:
+        pytest.skip("not enough free device memory")
+    pr = W.random_problem(n, W.SplitMix64(910), "3reg", False)
+    sim = q.Simulator(n, pr.edges, None, "c64")
+    v, z = sim.max_cut()
+    sim.close()
+    # the reported maximiser attains the value, and no single-vertex move improves it
+    e = pr.edges
+    cut = lambda x: int(sum(((x >> int(u)) ^ (x >> int(w))) & 1 for u, w in e))
+    assert cut(z) == v and z < (1 << 31)
+    assert all(cut(z ^ (1 << k)) <= v for k in range(n))
