@@ -108,31 +108,52 @@ __device__ __forceinline__ uint32_t tbase(uint32_t tid, int b) {
   return (tid & ((1u << b) - 1u)) | ((tid >> b) << (b + LOGR));
 }
 
-// Tile index -> memory offset: tile bits [0,L) stay, tile bits [L,K) go to [h, h+K-L).
-__device__ __forceinline__ uint64_t tmem(uint32_t t, int L, int h) {
-  return (uint64_t)(t & ((1u << L) - 1u)) | ((uint64_t)(t >> L) << h);
+// Memory offset of tile index t: tile bit i -> memory bit tpos[i] (bits of t
+// at KB and above are zero).  The positions are read as whole words.
+template <int KB>
+__device__ __forceinline__ uint64_t tmem(uint32_t t, const QCONST int8_t* tpos) {
+  const QCONST uint32_t* w = reinterpret_cast<const QCONST uint32_t*>(tpos);
+  uint32_t pw[(KB + 3) / 4];
+#pragma unroll
+  for (int i = 0; i < (KB + 3) / 4; ++i) pw[i] = w[i];
+  uint64_t r = 0;
+#pragma unroll
+  for (int i = 0; i < KB; ++i) r |= (uint64_t)((t >> i) & 1u) << ((pw[i >> 2] >> (8 * (i & 3))) & 63u);
+  return r;
 }
 
-// Memory offset of register index j in a round with register base b.
+// Memory offset of register index j: the OR of the memory bits (given as
+// masks) of the register bits set in j.
 template <int LOGR>
-__device__ __forceinline__ uint64_t moff(int j, int b, int L, int h) {
-  return tmem((uint32_t)j << b, L, h);
-}
+struct RegOffsets {
+  uint64_t bit[LOGR];
+  __device__ __forceinline__ explicit RegOffsets(const QCONST uint64_t* bits) {
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k) bit[k] = bits[k];
+  }
+  __device__ __forceinline__ uint64_t operator()(int j) const {
+    uint64_t o = 0;
+#pragma unroll
+    for (int k = 0; k < LOGR; ++k)
+      if ((j >> k) & 1) o |= bit[k];
+    return o;
+  }
+};
 
 template <typename R, int LOGR>
 __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const QGLOBAL cx<R>* __restrict__ src,
-                                          uint64_t zt, int b, int L, int h) {
+                                          uint64_t zt, const RegOffsets<LOGR>& ro) {
   const QGLOBAL cx<R>* base = src + zt;
 #pragma unroll
-  for (int j = 0; j < (1 << LOGR); ++j) v[j] = ldg(base + moff<LOGR>(j, b, L, h));
+  for (int j = 0; j < (1 << LOGR); ++j) v[j] = ldg(base + ro(j));
 }
 
 template <typename R, int LOGR>
 __device__ __forceinline__ void store_tile(const cx<R> (&v)[1 << LOGR], QGLOBAL cx<R>* __restrict__ dst,
-                                           uint64_t zt, int b, int L, int h) {
+                                           uint64_t zt, const RegOffsets<LOGR>& ro) {
   QGLOBAL cx<R>* base = dst + zt;
 #pragma unroll
-  for (int j = 0; j < (1 << LOGR); ++j) stg(base + moff<LOGR>(j, b, L, h), v[j]);
+  for (int j = 0; j < (1 << LOGR); ++j) stg(base + ro(j), v[j]);
 }
 
 // Move the register contents from round mapping `from` to round mapping `to` through LDS.
@@ -329,12 +350,7 @@ struct SiteVals {
 // w_uv (1 - 2 zbase_v).  It depends only on the graph and the tile
 // geometry, so it is tabulated once per qubit set (k_tile_cut) and read by
 // the pass kernels with uniform loads.
-__device__ __forceinline__ uint64_t zbase_of(int64_t g, int K, int L, int h) {
-  const int lowfree = h - L;
-  return (((uint64_t)g & ((1ull << lowfree) - 1ull)) << L) | (((uint64_t)g >> lowfree) << (h + K - L));
-}
-
-__global__ void __launch_bounds__(256) k_tile_cut(const GraphDev* __restrict__ gp, int K, int L, int h,
+__global__ void __launch_bounds__(256) k_tile_cut(const GraphDev* __restrict__ gp, int K, int nfree, TileMap map,
                                                   int64_t ntiles, double* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= ntiles) return;
@@ -344,17 +360,18 @@ __global__ void __launch_bounds__(256) k_tile_cut(const GraphDev* __restrict__ g
   const QCONST double* ew = cmem<double>(g_->ew);
   const QCONST int32_t* nbr = cmem<int32_t>(g_->nbr);
   const QCONST double* nw = cmem<double>(g_->nw);
-  const uint64_t zb = zbase_of(g, K, L, h);
+  uint64_t zb = 0, tmask = 0;
+  for (int i = 0; i < nfree; ++i) zb |= (((uint64_t)g >> i) & 1ull) << map.gpos[i];
+  for (int i = 0; i < K; ++i) tmask |= 1ull << map.tpos[i];
   double cb = 0.0;
   for (int e = 0; e < g_->m; ++e)
     if (((zb >> eu[e]) ^ (zb >> ev[e])) & 1ull) cb += ew[e];
-  const uint64_t tmask = ((1ull << L) - 1ull) | (((1ull << (K - L)) - 1ull) << h);
   double* row = out + g * kTileCutStride;
   row[0] = cb;
   for (int i = 0; i < kTileCutStride - 1; ++i) {
     double d = 0.0;
     if (i < K) {
-      const int u = i < L ? i : h + (i - L);
+      const int u = map.tpos[i];
       for (int k = g_->off[u]; k < g_->off[u + 1]; ++k) {
         const int v = nbr[k];
         if (!((tmask >> v) & 1ull)) d += ((zb >> v) & 1ull) ? -nw[k] : nw[k];
@@ -457,8 +474,13 @@ __device__ __forceinline__ int64_t tile_of_block(const PassDesc& D, int ndesc) {
   return wg - D.tile_begin;
 }
 
+// Memory offset of tile g's index-0 amplitude (scalar arithmetic on the
+// descriptor's runs, so the tile's loads can issue at once).
 __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
-  return zbase_of(g, D.K, D.L, D.h);
+  uint64_t z = 0;
+#pragma unroll
+  for (int r = 0; r < kMaxRuns; ++r) z |= ((uint64_t)g & D.map.gmask[r]) << D.map.gshift[r];
+  return z;
 }
 
 // One forward pass over one tile.  Template knobs, each either fixed at
@@ -476,26 +498,26 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
   const int64_t g = tile_of_block(D, ndesc);
-  const int L = D.L, h = D.h, nth = blockDim.x;
+  const int nth = blockDim.x;
   const int nr = NRC > 0 ? NRC : D.nrounds;
   const int nseg = NSC > 0 ? NSC : D.nseg;
   const int flags = D.flags;
   const bool gen = GEN >= 0 ? GEN != 0 : (flags & PF_GEN) != 0;
   const int exp = EXP >= 0 ? EXP : ((flags & PF_EXPECT) ? ((flags & PF_WRITE_LAM) ? 2 : 1) : 0);
-  const uint64_t zbase = tile_zbase(D, g);
   const QCONST cx<R>* __restrict__ ctab = cmem<cx<R>>(D.ctab);
   const QCONST SegDesc* __restrict__ segs = cmem<SegDesc>(D.segs);
   const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
   const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
 
-  const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
+  const RegOffsets<LOGR> ro0(cmem<uint64_t>(D.rbit0));
+  const uint64_t zt0 = tile_zbase(D, g) | tmem<KB>(tbase<LOGR>(tid, D.rb[0]), cmem<int8_t>(D.map.tpos));
   cx<R> v[NR];
   if (gen) {
     const R a = (R)D.amp0;
 #pragma unroll
     for (int j = 0; j < NR; ++j) v[j] = {a, (R)0};
   } else {
-    load_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, D.rb[0], L, h);
+    load_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, ro0);
   }
   // Site values: the per-thread cut decomposition; segment s uses site s & 1,
   // at the round it starts in, and <C> uses site 0.  Full-LDS kernels run two
@@ -592,7 +614,7 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
       aN += pr;
       if (exp == 2) {
         const cx<R> lv = {(R)(cj * v[J].re), (R)(cj * v[J].im)};
-        stg(lam + (zt0 | moff<LOGR>(J, D.rb[0], L, h)), lv);
+        stg(lam + (zt0 | ro0(J)), lv);
       }
     }
     block_reduce2(aE, aN, red, blockDim.x);
@@ -602,7 +624,7 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
       part[D.ntiles + g] = aN;
     }
   }
-  if (!(flags & PF_NO_STORE)) store_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, D.rb[0], L, h);
+  if (!(flags & PF_NO_STORE)) store_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, ro0);
 }
 
 // Im sum over register pairs of conj(l_a) f_b + conj(l_b) f_a, for the qubits in mask.
@@ -648,12 +670,11 @@ k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
   const int64_t g = tile_of_block(D, ndesc);
-  const int L = D.L, h = D.h, nth = blockDim.x;
+  const int nth = blockDim.x;
   const int nr = NRC > 0 ? NRC : D.nrounds;
   const int nseg = NSC > 0 ? NSC : D.nseg;
   const bool nostore = NOSTORE >= 0 ? NOSTORE != 0 : (D.flags & PF_NO_STORE) != 0;
   const int64_t nt = D.ntiles;
-  const uint64_t zbase = tile_zbase(D, g);
   QGLOBAL cx<R>* __restrict__ phi = gmem<cx<R>>(D.psi);
   QGLOBAL cx<R>* __restrict__ lamp = gmem<cx<R>>(D.lam);
   QGLOBAL double* __restrict__ part = gmem<double>(D.part);
@@ -662,10 +683,11 @@ k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
   const QCONST double* __restrict__ dtab = cmem<double>(D.dtab);
   const QCONST double* __restrict__ tcrow = cmem<double>(D.tcut) + g * kTileCutStride;
 
-  const uint64_t zt0 = zbase | tmem(tbase<LOGR>(tid, D.rb[0]), L, h);
+  const RegOffsets<LOGR> ro0(cmem<uint64_t>(D.rbit0));
+  const uint64_t zt0 = tile_zbase(D, g) | tmem<KB>(tbase<LOGR>(tid, D.rb[0]), cmem<int8_t>(D.map.tpos));
   cx<R> f[NR], l[NR];
-  load_tile<R, LOGR>(f, phi, zt0, D.rb[0], L, h);
-  load_tile<R, LOGR>(l, lamp, zt0, D.rb[0], L, h);
+  load_tile<R, LOGR>(f, phi, zt0, ro0);
+  load_tile<R, LOGR>(l, lamp, zt0, ro0);
 
   auto has_phase = [&](int s) __attribute__((always_inline)) {
     return PHM >= 0 ? ((PHM >> s) & 1) != 0 : segs[s].has_phase != 0;
@@ -750,8 +772,8 @@ k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
     // instead of keeping all load addresses of both vectors live meanwhile.
     uint64_t zs = zt0;
     asm volatile("" : "+v"(zs));
-    store_tile<R, LOGR>(f, phi, zs, D.rb[0], L, h);
-    store_tile<R, LOGR>(l, lamp, zs, D.rb[0], L, h);
+    store_tile<R, LOGR>(f, phi, zs, ro0);
+    store_tile<R, LOGR>(l, lamp, zs, ro0);
   }
 }
 
@@ -1008,9 +1030,10 @@ hipError_t launch_reverse(int prec, void* x, int64_t N, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_tile_cut(const GraphDev* g, int K, int L, int h, int64_t ntiles, double* out, hipStream_t st) {
+hipError_t launch_tile_cut(const GraphDev* g, int K, int nfree, const TileMap& map, int64_t ntiles, double* out,
+                           hipStream_t st) {
   const int64_t blocks = (ntiles + 255) / 256;
-  hipLaunchKernelGGL(k_tile_cut, dim3((unsigned)blocks), dim3(256), 0, st, g, K, L, h, ntiles, out);
+  hipLaunchKernelGGL(k_tile_cut, dim3((unsigned)blocks), dim3(256), 0, st, g, K, nfree, map, ntiles, out);
   return hipGetLastError();
 }
 

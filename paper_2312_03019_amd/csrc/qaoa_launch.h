@@ -38,7 +38,8 @@ hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, 
 hipError_t launch_reverse(int prec, void* x, int64_t N, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
 // Per-tile cut table (kTileCutStride doubles per tile) of one qubit set.
-hipError_t launch_tile_cut(const GraphDev* g, int K, int L, int h, int64_t ntiles, double* out, hipStream_t st);
+hipError_t launch_tile_cut(const GraphDev* g, int K, int nfree, const TileMap& map, int64_t ntiles, double* out,
+                           hipStream_t st);
 
 // Gate-by-gate circuit (Algorithm 1): |0> -> H on every qubit -> per level one
 // diagonal sweep per edge and one RX sweep per qubit.  Host arrays, canonical

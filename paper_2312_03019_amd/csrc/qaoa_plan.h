@@ -4,8 +4,8 @@
 // on-chip memory one tile at a time: a tile is 2^K amplitudes whose indices
 // differ in a fixed set of K bits (the "tile bits"), the rest of the index
 // (the tile id) being fixed.  Tile bits [0, L) are memory bits [0, L)
-// (contiguous, so loads coalesce); tile bits [L, K) are memory bits
-// [h, h + K - L).  Inside the tile, each thread holds 2^LOGR amplitudes in
+// (contiguous, so loads coalesce); where the others go is the set's TileMap.
+// Inside the tile, each thread holds 2^LOGR amplitudes in
 // registers whose indices differ in LOGR consecutive tile bits [b, b + LOGR)
 // (a "round"); LDS transposes move from one round's register bits to the
 // next.  The mixer qubits of a pass are applied round by round.
@@ -28,6 +28,22 @@ constexpr int kMaxLogR = 5;
 constexpr int kMaxRounds = 4;
 constexpr int kMaxN = 34;
 constexpr int kMaxThreads = 256;
+constexpr int kMaxTileBits = 16;
+
+// Where a tile sits in the state: tile bit i is memory (qubit) bit tpos[i],
+// bit i of the tile index g is memory bit gpos[i], and the two lists
+// together cover every memory bit once.  A tile's passengers (low memory
+// bits carried along for coalescing) are its lowest tile bits.  The index
+// map is also kept as runs of consecutive bits, so a tile's base offset is
+// OR over r of (g & gmask[r]) << gshift[r] (unused runs have gmask 0).
+constexpr int kMaxRuns = 12;
+struct alignas(8) TileMap {
+  uint64_t gmask[kMaxRuns];
+  int8_t gshift[kMaxRuns];
+  int8_t tpos[kMaxTileBits];
+  int8_t gpos[kMaxN];
+  int8_t pad[2];
+};
 
 // Graph in device memory.  Masks hold one bit per vertex.
 struct GraphDev {
@@ -105,7 +121,9 @@ struct PassDesc {
   double *part;             // partial-sum slots: part[slot * ntiles + tile]
   int64_t tile_begin;       // first workgroup of this descriptor within the launch
   int64_t ntiles;
-  int32_t n, K, L, h;
+  int32_t n, K;
+  int32_t nfree;            // tile-index bits: n - K
+  int32_t pad0_;
   int32_t nrounds;
   int32_t rb[kMaxRounds];   // register-bit base of each round
   int32_t rxmask[kMaxRounds];  // which register bits get the mixer in that round
@@ -117,6 +135,8 @@ struct PassDesc {
   double amp0;              // 2^(-n/2)
   double fscale_re, fscale_im;  // pending mixer scalars, applied at the end when PF_SCALE
   const double *tcut;       // per tile: C(zbase), dout[0..K) (kTileCutStride doubles each)
+  TileMap map;
+  uint64_t rbit0[kMaxLogR];  // memory bit (as a mask) of each register bit of round 0
 };
 
 // Per-tile cut table row: [C(zbase), dout_0 .. dout_{K-1}, 0...].

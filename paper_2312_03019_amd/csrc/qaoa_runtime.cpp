@@ -167,33 +167,76 @@ static void make_rounds(SetGeom& s, int sL, int logr, int overlap) {
   }
 }
 
+// Tile map of a set whose tile bit i is memory bit mem[i]; the tile index
+// takes the remaining memory bits in ascending order.  False if the index
+// map needs more than kMaxRuns runs.
+static bool tile_map(int n, const std::vector<int>& mem, TileMap* m) {
+  memset(m, 0, sizeof *m);
+  uint64_t used = 0;
+  for (size_t i = 0; i < mem.size(); ++i) {
+    m->tpos[i] = (int8_t)mem[i];
+    used |= 1ull << mem[i];
+  }
+  int k = 0, r = -1;
+  for (int b = 0; b < n; ++b) {
+    if ((used >> b) & 1ull) continue;
+    m->gpos[k] = (int8_t)b;
+    if (k == 0 || m->gpos[k - 1] != b - 1) {   // a new run starts at index bit k
+      if (++r == kMaxRuns) return false;
+      m->gshift[r] = (int8_t)(b - k);
+    }
+    m->gmask[r] |= 1ull << k;
+    ++k;
+  }
+  return true;
+}
+
+// Memory layout of the low set (all tile bits are qubits [0, K)).  In round 0
+// a thread's tile bits are [0, K - logr): lanes [0, 6), the wave index above
+// them, the registers on top.  Placing the register bits right above the lane
+// bits and the wave bits at the top makes each wave's loads cover one
+// contiguous block of 64 * 2^logr amplitudes.
+static std::vector<int> low_set_bits(int K, int logr) {
+  const int t0 = K - logr, lanes = t0 < 6 ? t0 : 6, w = t0 - lanes;
+  std::vector<int> mem(K);
+  for (int i = 0; i < K; ++i) mem[i] = i < lanes ? i : (i < t0 ? i + logr : i - w);
+  return mem;
+}
+
+// The qubits above the low set are dealt to the high sets in turn (set j
+// takes K + j, K + j + mh, ...).  Each high tile then spreads over every
+// part of the address range in similar measure; a set made of the top
+// qubits alone sends a tile's 2^(K-L) runs to addresses 2^(n-k) apart
+// across the whole state, which HBM serves markedly slower.
 std::vector<SetGeom> make_sets(int n, const PrecCfg& pc) {
   int K, logr;
   tile_shape(n, pc, &K, &logr);
   const int ov = half_tile_rounds(K, logr, pc) ? 1 : 0;
   std::vector<SetGeom> sets;
-  if (n <= pc.kmax) {
-    SetGeom s{};
-    s.K = n; s.L = n; s.h = n; s.k = n;
-    make_rounds(s, 0, logr, ov);
-    sets.push_back(s);
-    return sets;
-  }
   SetGeom a{};
-  a.K = K; a.L = K; a.h = K; a.k = K;
+  a.K = K; a.L = K; a.k = K;
+  tile_map(n, low_set_bits(K, logr), &a.map);   // one run
   make_rounds(a, 0, logr, ov);
   sets.push_back(a);
+  if (n <= pc.kmax) return sets;
   const int rem = n - K, cap = K - pc.passenger;
   const int mh = (rem + cap - 1) / cap;
-  const int base = rem / mh, extra = rem % mh;
   int start = K;
   for (int i = 0; i < mh; ++i) {
-    const int k = base + (i < extra ? 1 : 0);
+    const int k = (n - K) / mh + (i < (n - K) % mh ? 1 : 0);
     SetGeom s{};
-    s.K = K; s.k = k; s.L = K - k; s.h = start;
+    s.K = K; s.k = k; s.L = K - k;
+    std::vector<int> mem;
+    for (int t = 0; t < s.L; ++t) mem.push_back(t);
+    for (int t = K + i; t < n; t += mh) mem.push_back(t);
+    if (!tile_map(n, mem, &s.map)) {          // too many index runs: a contiguous block
+      mem.resize(s.L);
+      for (int t = start; t < start + k; ++t) mem.push_back(t);
+      tile_map(n, mem, &s.map);
+    }
+    start += k;
     make_rounds(s, s.L, logr, ov);
     sets.push_back(s);
-    start += k;
   }
   return sets;
 }
@@ -238,7 +281,7 @@ std::vector<PassSpec> make_schedule(int nsets, int p) {
 }
 
 // Memory bit carried by tile bit t.
-static int tile_to_mem(const SetGeom& s, int t) { return t < s.L ? t : s.h + (t - s.L); }
+static int tile_to_mem(const SetGeom& s, int t) { return s.map.tpos[t]; }
 
 // Host tables of one round mapping (see SiteDesc): RT over the register
 // vertices, and per thread F and G over the thread's set tile vertices.
@@ -248,15 +291,15 @@ static SiteDesc make_site(const SetGeom& s, int round, int logr, const HostGraph
   const int b = s.rb[round];
   const int K = s.K;
   const int nth = 1 << (K - logr);
-  int tpos[64];                 // tile bit of each vertex, -1 outside the tile
-  for (int v = 0; v < 64; ++v) tpos[v] = -1;
-  for (int i = 0; i < K; ++i) tpos[tile_to_mem(s, i)] = i;
+  int vtile[64];                // tile bit of each vertex, -1 outside the tile
+  for (int v = 0; v < 64; ++v) vtile[v] = -1;
+  for (int i = 0; i < K; ++i) vtile[tile_to_mem(s, i)] = i;
   for (int k = 0; k < logr; ++k) sd.q[k] = tile_to_mem(s, b + k);
   const int NR = 1 << logr;
   sd.rt_off = (int32_t)dtab.size();
   std::vector<double> rt(NR, 0.0);
   for (int e = 0; e < hg.m(); ++e) {
-    const int iu = tpos[hg.eu[e]], iv = tpos[hg.ev[e]];
+    const int iu = vtile[hg.eu[e]], iv = vtile[hg.ev[e]];
     if (iu < b || iu >= b + logr || iv < b || iv >= b + logr) continue;
     const int ku = iu - b, kv = iv - b;
     for (int J = 0; J < NR; ++J)
@@ -267,7 +310,7 @@ static SiteDesc make_site(const SetGeom& s, int round, int logr, const HostGraph
   std::vector<int> ti, tj;
   std::vector<double> tw;
   for (int e = 0; e < hg.m(); ++e) {
-    const int iu = tpos[hg.eu[e]], iv = tpos[hg.ev[e]];
+    const int iu = vtile[hg.eu[e]], iv = vtile[hg.ev[e]];
     if (iu < 0 || iv < 0) continue;
     ti.push_back(iu);
     tj.push_back(iv);
@@ -363,8 +406,9 @@ void build_run(const RunRequest& rq, RunImage* img) {
     memset(&d, 0, sizeof d);
     d.n = n;
     d.K = s.K;
-    d.L = s.L;
-    d.h = s.h;
+    d.nfree = n - s.K;
+    d.map = s.map;
+    for (int k = 0; k < logr; ++k) d.rbit0[k] = 1ull << s.map.tpos[s.rb[0] + k];
     d.nrounds = s.nr;
     for (int r = 0; r < s.nr; ++r) {
       d.rb[r] = s.rb[r];
@@ -569,7 +613,7 @@ hipError_t launch_tile_cuts(int n, int prec, const GraphDev* g, double* tcut, hi
   const int64_t ntiles = (int64_t)1 << (n - K);
   const std::vector<SetGeom> sets = make_sets(n, pc);
   for (size_t k = 0; k < sets.size(); ++k) {
-    hipError_t e = launch_tile_cut(g, sets[k].K, sets[k].L, sets[k].h, ntiles,
+    hipError_t e = launch_tile_cut(g, sets[k].K, n - sets[k].K, sets[k].map, ntiles,
                                    tcut + (int64_t)k * ntiles * kTileCutStride, st);
     if (e != hipSuccess) return e;
   }

@@ -39,7 +39,8 @@ void build_dev_graph_image(const HostGraph& hg, void* host_buf, void* dev_base);
 
 // The qubit sets the mixer is split into and their tile geometry.
 struct SetGeom {
-  int K, L, h, k;               // tile bits, low tile bits, start of high block, qubits in set
+  int K, L, k;                  // tile bits, passenger tile bits, qubits in set
+  TileMap map;                  // where tile bits and tile-index bits sit in memory
   int nr;                       // rounds
   int rb[kMaxRounds];
   int rxmask[kMaxRounds];

@@ -23,8 +23,12 @@ import paper_2312_03019_amd as q  # noqa: E402
 
 def _accurate_cdf(psi, chunk=4096):
     """The CDF with small rounding at any size: pairwise sums per chunk, a
-    compensated running sum over the chunks, then in-chunk cumulative sums."""
-    p = np.abs(np.asarray(psi)).astype(np.float64) ** 2
+    compensated running sum over the chunks, then in-chunk cumulative sums.
+    Each |psi_z|^2 is the exact FP64 sum of the squared components (abs() of
+    a complex64 array would round the magnitude to float32 first)."""
+    psi = np.asarray(psi)
+    p = psi.real.astype(np.float64) ** 2
+    p += psi.imag.astype(np.float64) ** 2
     n = len(p)
     if n <= chunk:
         return np.cumsum(p)
