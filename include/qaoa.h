@@ -161,6 +161,17 @@ int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count
  * mixer is split into, and the qubits per set (sizes[] up to max_sets). */
 int qaoa_plan_info(qaoa_ctx *ctx, int p, int *passes, int *sets, int *sizes, int max_sets);
 
+/* Memory layout of qubit set `set` (0 = the low set) of an n-qubit plan in
+ * precision prec, for inspection and tests; needs no GPU and no context.
+ * Writes the tile-bit count K to *k_out, then tpos[0..K): the memory bit of
+ * each tile bit, gpos[0..n-K): the memory bit of each tile-index bit, and
+ * (if not NULL) the same index map as runs, gmask[0..12) / gshift[0..12):
+ * base offset of tile g = OR over r of (g & gmask[r]) << gshift[r].  tpos
+ * needs 16 entries, gpos 64.  QAOA_EINVAL for n outside [1, 34] or a set
+ * the plan does not have. */
+int qaoa_tile_map(int n, int prec, int set, int *k_out, int8_t *tpos, int8_t *gpos, uint64_t *gmask,
+                  int8_t *gshift);
+
 /* Bandwidth reference: copy bytes (a multiple of 16) from src to dst, both
  * device pointers, with a plain streaming kernel on the given stream. */
 int qaoa_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);

@@ -81,6 +81,8 @@ _SIGS = {
     "qaoa_set_profiling": (_I, [_P, _I]),
     "qaoa_pass_times": (_I, [_P, ctypes.POINTER(ctypes.c_float), _DP, _I, ctypes.POINTER(_I)]),
     "qaoa_plan_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I), _I]),
+    "qaoa_tile_map": (_I, [_I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(ctypes.c_int8),
+                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int8)]),
     "qaoa_copy_probe": (_I, [_P, _P, _SZ, _P]),
     "qaoa_last_error": (ctypes.c_char_p, []),
     "qaoa_serve_create": (_I, [_SZ, _I, _I, ctypes.POINTER(_P)]),
@@ -252,6 +254,20 @@ def qaoa_plan_info(ctx, p: int):
     sizes = (ctypes.c_int * 64)()
     _err(_lib.qaoa_plan_info(ctx, int(p), ctypes.byref(passes), ctypes.byref(sets), sizes, 64))
     return passes.value, list(sizes[:sets.value])
+
+
+def qaoa_tile_map(n: int, prec: str, set_index: int):
+    """Memory layout of one qubit set: (tpos, gpos, gmask, gshift) as numpy arrays
+    (tile bit -> memory bit, tile-index bit -> memory bit, and the index map as runs)."""
+    k = ctypes.c_int()
+    tp = (ctypes.c_int8 * 16)()
+    gp = (ctypes.c_int8 * 64)()
+    gm = (ctypes.c_uint64 * 12)()
+    gs = (ctypes.c_int8 * 12)()
+    _err(_lib.qaoa_tile_map(int(n), _PREC[prec], int(set_index), ctypes.byref(k), tp, gp, gm, gs))
+    K = k.value
+    return (np.array(tp[:K], dtype=np.int64), np.array(gp[:n - K], dtype=np.int64),
+            np.array(gm[:], dtype=np.uint64), np.array(gs[:], dtype=np.int64))
 
 
 def qaoa_copy_probe(src, dst, nbytes: int, stream=None) -> None:

@@ -604,6 +604,28 @@ int qaoa_plan_info(qaoa_ctx* c, int p, int* passes, int* sets, int* sizes, int m
   return QAOA_OK;
 }
 
+int qaoa_tile_map(int n, int prec, int set, int* k_out, int8_t* tpos, int8_t* gpos, uint64_t* gmask,
+                  int8_t* gshift) {
+  if (n < 1 || n > kMaxN || (prec != QAOA_C64 && prec != QAOA_C128) || !k_out || !tpos || !gpos) {
+    set_error("invalid arguments");
+    return QAOA_EINVAL;
+  }
+  const std::vector<SetGeom> s = make_sets(n, prec_cfg(prec));
+  if (set < 0 || set >= (int)s.size()) {
+    set_error("the plan has %d qubit sets", (int)s.size());
+    return QAOA_EINVAL;
+  }
+  const SetGeom& g = s[set];
+  *k_out = g.K;
+  for (int i = 0; i < g.K; ++i) tpos[i] = g.map.tpos[i];
+  for (int i = 0; i < n - g.K; ++i) gpos[i] = g.map.gpos[i];
+  for (int r = 0; gmask && gshift && r < kMaxRuns; ++r) {
+    gmask[r] = g.map.gmask[r];
+    gshift[r] = g.map.gshift[r];
+  }
+  return QAOA_OK;
+}
+
 int qaoa_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
   if (!src || !dst || bytes == 0 || bytes % 16) {
     set_error("copy probe needs non-NULL pointers and a multiple of 16 bytes");
