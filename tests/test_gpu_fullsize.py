@@ -215,3 +215,32 @@ def test_max_cut_n32_is_a_valid_maximum():
     cut = lambda x: int(sum(((x >> int(u)) ^ (x >> int(w))) & 1 for u, w in e))
     assert cut(z) == v and z < (1 << 31)
     assert all(cut(z ^ (1 << k)) <= v for k in range(n))
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_every_size_14_to_29_against_closed_form_and_light_cone(prec):
+    """Every plan shape between one tile and the full workload (one, two or three
+    qubit sets; 4 to 6 passengers; interleaved high sets): weighted 3-regular
+    graphs (odd n: one isolated vertex more), p=1 closed form and exact p=2
+    light cone."""
+    worst = 0.0
+    for n in range(14, 30):
+        base = W.random_problem(n - (n & 1), W.SplitMix64(950 + n), "3reg", True)
+        pr = W.Problem(n, base.edges, base.weights, f"w3reg{n - (n & 1)}+{n & 1}")
+        g, b = W.uniform_angles(2, W.SplitMix64(951 + n))
+        sim = q.Simulator(n, pr.edges, pr.weights, prec)
+        try:
+            e1, nrm = sim.expect(g[:1], b[:1])
+            e2, _ = sim.expect(g, b)
+            sizes = sim.plan(2)[1]
+        finally:
+            sim.close()
+        cf = oracle.closed_form_p1(n, pr.edges, pr.weights, g[0], b[0])
+        lc = oracle.light_cone_expect(n, pr.edges, pr.weights, g, b, _zz)
+        err = max(abs(e1 - cf), abs(e2 - lc))
+        worst = max(worst, err / pr.num_edges)
+        print(f"n={n} {prec} sets {sizes}: p=1 {e1!r} vs {cf!r}, p=2 {e2!r} vs {lc!r}")
+        assert abs(e1 - cf) <= _tol(prec, pr.num_edges)
+        assert abs(e2 - lc) <= _tol(prec, pr.num_edges)
+        assert abs(nrm - 1) <= (1e-12 if prec == "c128" else 1e-5)
+    print(f"{prec}: worst error / |E| = {worst:.2e}")
