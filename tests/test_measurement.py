@@ -1,0 +1,74 @@
+"""Host-side checks of the measurement plumbing (no GPU): bench.py's contract
+on the GPU count and its counter-traffic lookup, and the arithmetic of the
+rocprofv3 counter summary (FETCH_SIZE / WRITE_SIZE scaled by what the same
+counters read for a copy kernel of known size)."""
+import argparse
+import hashlib
+import importlib.util
+import json
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SRC = os.path.join(ROOT, "paper_2312_03019_amd", "csrc", "qaoa_kernels.hip")
+
+
+def _load(name, path):
+    spec = importlib.util.spec_from_file_location(name, path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_counter_traffic_is_used_only_for_the_current_kernel(tmp_path):
+    bench = _load("bench_under_test", os.path.join(ROOT, "bench.py"))
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    good = tmp_path / "good.md"
+    good.write_text(f"text\n- traffic_bytes_per_launch: 1.5e+10\n- kernel_source_sha256: {sha}\n")
+    t, src = bench.pmc_traffic(str(good))
+    assert t == 1.5e10 and src.endswith("good.md")
+    stale = tmp_path / "stale.md"
+    stale.write_text("- traffic_bytes_per_launch: 1.5e+10\n- kernel_source_sha256: " + "0" * 64 + "\n")
+    t, src = bench.pmc_traffic(str(stale))
+    assert t is None and "changed" in src
+    t, src = bench.pmc_traffic(str(tmp_path / "missing.md"))
+    assert t is None
+
+
+def _pmc_csv(path, counter, rows):
+    with open(path, "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for d, name, v in rows:
+            f.write(f'{d},"{name}",{counter},{v}\n')
+
+
+def test_counter_summary_scales_by_the_copy_kernel(tmp_path, capsys):
+    ps = _load("profile_summary_under_test", os.path.join(ROOT, "paper_2312_03019_amd", "profile_summary.py"))
+    copy = "qaoa::k_copy(HIP_vector_type<float, 4u> const*, HIP_vector_type<float, 4u>*, long)"
+    fwd = "void qaoa::k_fwd<float, 5, 13, 3, 1, 0, 0, 0, 1>(qaoa::PassDesc const*, int)"
+    # the copy moves 1 MiB each way; FETCH_SIZE reports half the bytes read (split over two
+    # rows of one dispatch), WRITE_SIZE all of the bytes written
+    _pmc_csv(tmp_path / "f.csv", "FETCH_SIZE", [(1, copy, 300.0), (1, copy, 212.0), (2, fwd, 1000.0), (3, fwd, 1200.0)])
+    _pmc_csv(tmp_path / "w.csv", "WRITE_SIZE", [(1, copy, 1024.0), (2, fwd, 1500.0), (3, fwd, 1700.0)])
+    a = argparse.Namespace(fetch=str(tmp_path / "f.csv"), write=str(tmp_path / "w.csv"), copy_bytes=float(1 << 20),
+                           alg_bytes=0.0, cmd="synthetic")
+    ps.counters(a)
+    out = capsys.readouterr().out
+    fields = dict(re.findall(r"^- (\w+): (\S+)$", out, re.M))
+    assert float(fields["fetch_scale"]) == pytest.approx(2.0)
+    assert float(fields["write_scale"]) == pytest.approx(1.0)
+    # mean over the two k_fwd dispatches: 1100 KiB fetched (x2), 1600 KiB written (x1)
+    assert float(fields["traffic_bytes_per_launch"]) == pytest.approx((1100.0 * 2 + 1600.0) * 1024, rel=1e-6)
+    assert fields["kernel_source_sha256"] == hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
