@@ -73,6 +73,19 @@ def time_runs(q, torch, sim, g, b, steps, warmup):
     return t, e, nrm, np.array(ms_all), np.array(by_all)
 
 
+def pass_kinds(pass_ms):
+    """Mean kernel ms per kind of pass in the three-set schedule (high set
+    first, low set, high set with two layers' segments, ..., high set last):
+    the write-only first pass, the low-set passes, the merged high-set passes
+    and the last pass (with <C>)."""
+    ms = list(pass_ms)
+    if len(ms) < 3:
+        return {"all": ms}
+    mid = ms[1:-1]
+    return {"first": ms[0], "low_set": float(np.mean(mid[0::2])),
+            "high_set_merged": float(np.mean(mid[1::2])) if len(mid) > 1 else None, "last": ms[-1]}
+
+
 def pmc_traffic(path):
     """Scaled HBM bytes per forward-pass launch from a committed rocprofv3
     counter summary, or None when the kernel source changed since it was taken."""
@@ -365,6 +378,7 @@ def main():
                         "algorithmic_bytes_per_launch": r64["launch_bytes_mean"],
                         "mean_launch_ms": r64["launch_ms_mean"],
                         "copy_ceiling_gbps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                        "pass_ms_by_kind": pass_kinds(r64["pass_ms"]) if len(r64["sets"]) == 3 else None,
                         "per_launch_bytes": "2*2^n*8 read+write (write-only 2^n*8 for the first pass)"}
     if not a.no_grad:
         line["grad"] = grad_bench(q, torch, W)
