@@ -340,18 +340,19 @@ int qaoa_sample(qaoa_ctx* c, int64_t count, const double* uniforms, uint64_t* ou
   }
   const int n = c->hg.n;
   const int64_t nc = sample_chunks(n);
-  const size_t bytes = (size_t)(2 * nc + 1) * 8 + (size_t)count * 16;
+  const size_t bytes = (size_t)(66 * nc + 1) * 8 + (size_t)count * 16;
   char* tmp = nullptr;
   HIPCHK(hipMalloc((void**)&tmp, bytes));
   double* sums = (double*)tmp;
   double* prefix = sums + nc;
-  double* du = prefix + nc + 1;
+  double* bsums = prefix + nc + 1;
+  double* du = bsums + 64 * nc;
   uint64_t* dout = (uint64_t*)(du + count);
   hipError_t e = hipSuccess;
   if (count > 0) e = hipMemcpyAsync(du, uniforms, (size_t)count * 8, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
-    e = launch_sample(c->prec == QAOA_C64 ? 1 : 0, c->psi, n, c->complemented ? 1 : 0, sums, prefix, du, count, dout,
-                      c->stream);
+    e = launch_sample(c->prec == QAOA_C64 ? 1 : 0, c->psi, n, c->complemented ? 1 : 0, sums, prefix, bsums, du, count,
+                      dout, c->stream);
   if (e == hipSuccess && count > 0) e = hipMemcpyAsync(out, dout, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(tmp);

@@ -219,10 +219,13 @@ __global__ void __launch_bounds__(64) k_max_final(const double* __restrict__ pv,
 // Sampling z with probability |psi_z|^2 / sum |psi|^2 by inverse CDF over the
 // natural index order: sample = min{z : CDF(z) > u * total}, for uniforms u in
 // [0, 1) supplied by the caller.  `rev` reads a complemented state (stored at
-// N-1-z).  Chunks of kChunk amplitudes: per-chunk sums (fixed order), their
-// exclusive prefix (one workgroup, fixed order), then one wave per sample:
-// binary search over the chunk prefix, lane sums of 64 amplitudes each, a
-// wave prefix, and a scan of the one lane that holds the target.
+// N-1-z).  Chunks of kChunk amplitudes: one pass over the state gives the
+// per-chunk sums and, inside each chunk, the sums of its 64 blocks of 64
+// amplitudes (fixed order); one workgroup turns the chunk sums into their
+// exclusive prefix.  Then each wave serves 64 samples: every lane binary-
+// searches the chunk prefix for its own sample, and per sample the wave reads
+// that chunk's 64 block sums, takes their prefix, and scans the one block
+// that holds the target, 64 amplitudes across the lanes.
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 4096;
 
@@ -234,12 +237,23 @@ __device__ __forceinline__ double prob_at(const typename V2<R>::T* psi, int64_t 
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_chunk_sums(const typename V2<R>::T* __restrict__ psi, int64_t N, int rev,
-                                                    double* __restrict__ sums) {
+                                                    double* __restrict__ sums, double* __restrict__ bsums) {
+  __shared__ double pv[kChunk + kChunk / 64];   // one pad slot per 64 keeps the block walks conflict-free
   __shared__ double red[256];
   const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-  const int64_t len = N - c0 < kChunk ? N - c0 : kChunk;
+  const int len = N - c0 < kChunk ? (int)(N - c0) : kChunk;
+  for (int i = threadIdx.x; i < len; i += 256) pv[i + (i >> 6)] = prob_at<R>(psi, N, rev, c0 + i);
+  __syncthreads();
+  if (threadIdx.x < 64) {   // block sums, each in index order
+    double a = 0.0;
+    for (int i = 0; i < 64; ++i) {
+      const int j = (int)threadIdx.x * 64 + i;
+      if (j < len) a += pv[j + (j >> 6)];
+    }
+    bsums[blockIdx.x * 64 + threadIdx.x] = a;
+  }
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < len; i += 256) s += prob_at<R>(psi, N, rev, c0 + i);
+  for (int i = threadIdx.x; i < len; i += 256) s += pv[i + (i >> 6)];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
@@ -280,60 +294,61 @@ __global__ void __launch_bounds__(1024) k_scan_chunks(const double* __restrict__
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_sample(const typename V2<R>::T* __restrict__ psi, int64_t N, int rev,
-                                                const double* __restrict__ prefix, int64_t nc,
-                                                const double* __restrict__ u, int64_t count,
+                                                const double* __restrict__ prefix, const double* __restrict__ bsums,
+                                                int64_t nc, const double* __restrict__ u, int64_t count,
                                                 uint64_t* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per sample
-  if (k >= count) return;
+  const int64_t k0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;   // this wave's 64 samples
   // (kept below the total, so trailing chunks without mass are never chosen)
   const double total = prefix[nc];
-  double t = u[k] * total;
+  const int64_t kl = k0 + lane;
+  double t = kl < count ? u[kl] * total : 0.0;
   if (t >= total) t = nextafter(total, 0.0);
-  // last chunk c with prefix[c] <= t (prefix is non-decreasing, prefix[0] = 0)
+  // last chunk c with prefix[c] <= t (prefix is non-decreasing, prefix[0] = 0), one search per lane
   int64_t lo = 0, hi = nc - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
     if (prefix[mid] <= t) lo = mid;
     else hi = mid - 1;
   }
-  const int64_t c0 = lo * kChunk;
-  const int64_t len = N - c0 < kChunk ? N - c0 : kChunk;
-  const int per = kChunk / 64;
-  double ls = 0.0;
-  for (int i = 0; i < per; ++i) {
-    const int64_t j = (int64_t)lane * per + i;
-    if (j < len) ls += prob_at<R>(psi, N, rev, c0 + j);
-  }
-  double incl = ls;   // inclusive wave prefix of the lane sums
-  for (int off = 1; off < 64; off <<= 1) {
-    const double y = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += y;
-  }
-  const double tl = t - prefix[lo];
-  // The first lane whose inclusive sum exceeds the target holds the sample.
-  // If rounding (these sums are re-added in another order than the chunk
-  // sums) leaves no such lane, the sample is the chunk's last element with
-  // nonzero probability, found in the highest lane with mass.
-  const unsigned long long ball = __ballot(incl > tl);
-  const bool found = ball != 0ull;
-  const unsigned long long mass = __ballot(ls > 0.0);
-  const int L = found ? __ffsll(ball) - 1 : (mass ? 63 - __clzll(mass) : 0);
-  if (lane == L) {
-    double run = incl - ls;
-    int64_t last = -1;   // last index with nonzero probability seen so far
-    for (int i = 0; i < per; ++i) {
-      const int64_t j = (int64_t)L * per + i;
-      if (j >= len) break;
-      const double pz = prob_at<R>(psi, N, rev, c0 + j);
-      if (pz > 0.0) last = c0 + j;
-      run += pz;
-      if (found && run > tl) {
-        last = c0 + j;
-        break;
-      }
+  const int64_t my_c = lo;
+  const double my_tl = t - prefix[lo];
+  for (int smp = 0; smp < 64; ++smp) {   // uniform trip count: every lane takes part in every shuffle
+    const int64_t c = __shfl(my_c, smp, 64);
+    const double tl = __shfl(my_tl, smp, 64);
+    const int64_t c0 = c * kChunk;
+    const int64_t len = N - c0 < kChunk ? N - c0 : kChunk;
+    const double bs = bsums[c * 64 + lane];
+    double incl = bs;   // inclusive wave prefix of the block sums
+    for (int off = 1; off < 64; off <<= 1) {
+      const double y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
     }
-    out[k] = (uint64_t)(last >= 0 ? last : c0);
+    // The first block with mass whose inclusive sum exceeds the target holds
+    // the sample (the CDF only steps up at elements of nonzero probability;
+    // the lanes' sums associate differently, so an empty block can round one
+    // ulp above its predecessor).  If rounding (block sums re-added in another
+    // order than the chunk sums) leaves no such block, the sample is the
+    // chunk's last element with nonzero probability, found in the highest
+    // block with mass.
+    const unsigned long long ball = __ballot(bs > 0.0 && incl > tl);
+    const bool found = ball != 0ull;
+    const unsigned long long mass = __ballot(bs > 0.0);
+    const int L = found ? __ffsll(ball) - 1 : (mass ? 63 - __clzll(mass) : 0);
+    const double base = __shfl(incl - bs, L, 64);   // sum of the blocks before L
+    const int64_t j = (int64_t)L * 64 + lane;
+    const double pz = j < len ? prob_at<R>(psi, N, rev, c0 + j) : 0.0;
+    double run = pz;
+    for (int off = 1; off < 64; off <<= 1) {
+      const double y = __shfl_up(run, off, 64);
+      if (lane >= off) run += y;
+    }
+    run += base;
+    const unsigned long long hit = __ballot(found && pz > 0.0 && run > tl);
+    const unsigned long long nz = __ballot(pz > 0.0);
+    const int64_t z = hit ? c0 + (int64_t)L * 64 + (__ffsll(hit) - 1)
+                          : (nz ? c0 + (int64_t)L * 64 + (63 - __clzll(nz)) : c0);
+    if (lane == 0 && k0 + smp < count) out[k0 + smp] = (uint64_t)z;
   }
 }
 
@@ -385,24 +400,25 @@ hipError_t launch_expect_state(int prec, const GraphDev* g, const void* psi, int
 
 int64_t sample_chunks(int n) { return ((int64_t(1) << n) + kChunk - 1) / kChunk; }
 
-hipError_t launch_sample(int prec, const void* psi, int n, int rev, double* sums, double* prefix, const double* u,
-                         int64_t count, uint64_t* out, hipStream_t st) {
+hipError_t launch_sample(int prec, const void* psi, int n, int rev, double* sums, double* prefix, double* bsums,
+                         const double* u, int64_t count, uint64_t* out, hipStream_t st) {
   const int64_t N = int64_t(1) << n, nc = sample_chunks(n);
   if (prec == 1)
     hipLaunchKernelGGL(k_chunk_sums<float>, dim3((unsigned)nc), dim3(256), 0, st, (const V2<float>::T*)psi, N, rev,
-                       sums);
+                       sums, bsums);
   else
     hipLaunchKernelGGL(k_chunk_sums<double>, dim3((unsigned)nc), dim3(256), 0, st, (const V2<double>::T*)psi, N,
-                       rev, sums);
+                       rev, sums, bsums);
   hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, st, sums, nc, prefix);
   if (count > 0) {
-    const dim3 grid((unsigned)((count + 3) / 4));
+    const int64_t waves = (count + 63) / 64;
+    const dim3 grid((unsigned)((waves + 3) / 4));
     if (prec == 1)
-      hipLaunchKernelGGL(k_sample<float>, grid, dim3(256), 0, st, (const V2<float>::T*)psi, N, rev, prefix, nc, u,
-                         count, out);
+      hipLaunchKernelGGL(k_sample<float>, grid, dim3(256), 0, st, (const V2<float>::T*)psi, N, rev, prefix, bsums, nc,
+                         u, count, out);
     else
-      hipLaunchKernelGGL(k_sample<double>, grid, dim3(256), 0, st, (const V2<double>::T*)psi, N, rev, prefix, nc, u,
-                         count, out);
+      hipLaunchKernelGGL(k_sample<double>, grid, dim3(256), 0, st, (const V2<double>::T*)psi, N, rev, prefix, bsums,
+                         nc, u, count, out);
   }
   return hipGetLastError();
 }

@@ -58,10 +58,10 @@ hipError_t launch_expect_state(int prec, const GraphDev* g, const void* psi, int
                                hipStream_t st);
 // Inverse-CDF samples of |psi|^2 in natural index order (rev: the state is
 // stored complemented).  sums: sample_chunks(n) doubles; prefix: one more;
-// u and out: count entries, device memory.
+// bsums: 64 per chunk; u and out: count entries, device memory.
 int64_t sample_chunks(int n);
-hipError_t launch_sample(int prec, const void* psi, int n, int rev, double* sums, double* prefix, const double* u,
-                         int64_t count, uint64_t* out, hipStream_t st);
+hipError_t launch_sample(int prec, const void* psi, int n, int rev, double* sums, double* prefix, double* bsums,
+                         const double* u, int64_t count, uint64_t* out, hipStream_t st);
 // Maximum cut value and its lowest index (pv / pz: one entry per block).
 hipError_t launch_max_cut(const GraphDev* g, int n, double* pv, uint64_t* pz, double* ov, uint64_t* oz,
                           hipStream_t st);

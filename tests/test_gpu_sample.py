@@ -69,7 +69,8 @@ def _check(psi, u, z, rel=1e-11):
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("seed,n,kind,weighted,beta1", [
-    (1, 1, "complete", False, 0.3), (2, 7, "gnp", True, 0.2), (3, 12, "3reg", False, 1.2), (4, 15, "gnp", True, 0.4),
+    (1, 1, "complete", False, 0.3), (9, 5, "gnp", True, 0.3), (2, 7, "gnp", True, 0.2), (3, 12, "3reg", False, 1.2),
+    (4, 15, "gnp", True, 0.4),
     (5, 18, "3reg", True, 1.3), (6, 21, "gnp", False, 0.7)])
 def test_samples_match_oracle(prec, seed, n, kind, weighted, beta1):
     pr = W.random_problem(n, W.SplitMix64(seed), kind, weighted, 0.4)
