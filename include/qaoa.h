@@ -119,7 +119,9 @@ int qaoa_max_cut(qaoa_ctx *ctx, double *value_out, uint64_t *argmax_out);
  * taken over z in natural order in FP64 (so the result is a deterministic
  * function of the caller's uniforms, each in [0, 1), else QAOA_EINVAL).
  * uniforms and out are host arrays of count entries.  QAOA_ESTATE without a
- * state (no run yet, or after qaoa_grad).  Synchronises the stream. */
+ * state (no run yet, or after qaoa_grad).  Allocates a device workspace of
+ * about 2^n / 8 + 16 * count bytes for the call (QAOA_EDEVICE if that
+ * fails).  Synchronises the stream. */
 int qaoa_sample(qaoa_ctx *ctx, int64_t count, const double *uniforms, uint64_t *out);
 
 /* Cut value C(z) for all 2^n z (the per-state totals of Algorithms 2/3, in the
