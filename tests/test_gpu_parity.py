@@ -128,7 +128,8 @@ def test_fidelity_c64_vs_c128():
     f = a.fidelity(c)
     ref = oracle.fidelity(20, a.state().astype(np.complex128), c.state())
     assert abs(f - ref) < 1e-12 and 1 - f <= 1e-5
-    assert abs(c.fidelity(c) - 1.0) < 1e-12 if False else True
+    c2 = q.Simulator(20, pr.edges, None, "c128").run(g, b)
+    assert abs(c.fidelity(c2) - 1.0) < 1e-12
 
 
 def test_bound_torch_state_and_stream():
@@ -188,3 +189,51 @@ def test_fidelity_between_complemented_and_plain_states():
     assert abs(a.fidelity(b) - ref) < 1e-12 and abs(b.fidelity(a) - ref) < 1e-12
     assert abs(c.fidelity(b) - ref) < 1e-5
     assert 1 - a.fidelity(c) < 1e-5
+
+
+# Plans with three qubit sets (complex64 from n = 23, complex128 from n = 22):
+# the low set runs second, two high sets take the upper qubits round-robin, and
+# their tile maps have several runs.  This is the plan shape of the n = 30
+# benchmark.  <C> and the gradient cannot see a permutation of the state that
+# keeps C (the global complement the shifted mixer form leaves, or a wrong
+# tile map that happens to preserve C), so the state is compared element by
+# element.  Angle sets give an odd and an even number of layers with
+# |sin beta| > |cos beta| (applied in the shifted form).
+_BETA_ODD = [0.3, 1.2, 0.5]            # one shifted layer -> stored complemented
+_BETA_EVEN = [1.0, 0.2, 1.3, 0.6]      # two shifted layers -> natural order
+
+
+@pytest.mark.parametrize("prec,n", [("c64", 23), ("c64", 24), ("c128", 22), ("c128", 23)])
+@pytest.mark.parametrize("beta", [_BETA_ODD, _BETA_EVEN], ids=["odd_shifted", "even_shifted"])
+def test_state_three_set_plan(prec, n, beta):
+    pr = _prob(300 + n, n, "3reg", True) if n % 2 == 0 else _prob(300 + n, n, "gnp", True, 0.2)
+    g = list(W.uniform_angles(len(beta), W.SplitMix64(400 + n))[0])
+    sim = q.Simulator(n, pr.edges, pr.weights, prec)
+    passes, sizes = sim.plan(len(beta))
+    assert len(sizes) == 3, sizes
+    sim.run(g, beta)
+    psi = sim.state().astype(np.complex128)
+    sim.close()
+    ref = oracle.evolve(n, pr.edges, pr.weights, g, beta)
+    err = float(np.max(np.abs(psi - ref)))
+    print(f"n={n} {prec} sets={sizes} passes={passes} beta={beta}: max|dpsi|={err:.3e}")
+    assert err < (1e-12 if prec == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("prec,n", [("c64", 24), ("c128", 22)])
+def test_bound_state_three_set_plan(prec, n):
+    pr = _prob(320 + n, n, "gnp", False, 0.3)
+    g = [0.45, 1.1, 0.8]
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    buf = torch.empty(1 << n, dtype=dt, device="cuda")
+    st = torch.cuda.Stream()
+    sim = q.Simulator(n, pr.edges, None, prec, stream=st)
+    q.qaoa_bind_state(sim.handle, buf)
+    e, _ = sim.expect(g, _BETA_ODD)
+    st.synchronize()
+    ref = oracle.evolve(n, pr.edges, None, g, _BETA_ODD)
+    err = float(np.max(np.abs(buf.cpu().numpy().astype(np.complex128) - ref)))
+    print(f"bound n={n} {prec}: max|dpsi|={err:.3e}")
+    assert err < (1e-12 if prec == "c128" else 1e-5)
+    assert abs(e - oracle.run_expect(n, pr.edges, None, g, _BETA_ODD)[0]) <= _tol(pr, prec)
+    sim.close()
