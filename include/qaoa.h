@@ -137,6 +137,20 @@ int qaoa_get_state(qaoa_ctx *ctx, void *host_out, size_t bytes);
  * same n (precisions may differ), accumulated in double on the device. */
 int qaoa_fidelity(qaoa_ctx *a, qaoa_ctx *b, double *f_out);
 
+/* qaoa_fidelity for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, computed by the same kernels in the same order (so equal
+ * bit for bit), but the per-block partial sums and reduction bookkeeping live
+ * in a static device buffer of 66 KiB that the library holds on each GPU it
+ * runs on until the process ends, instead of a per-call allocation.  The
+ * workspace needed is 32 bytes per block of 256 amplitudes, capped at 2048
+ * blocks (about 65 KiB) at every n; a size beyond the static buffer returns
+ * QAOA_EINVAL.  The first call on a device looks the buffer up (no
+ * allocation).  Both contexts must be on the same device.  Calls that
+ * overlap on one GPU (from several threads) share the buffer and race: the
+ * caller serialises them.  Synchronises a's stream. */
+int qaoa_fidelity_noalloc(qaoa_ctx *a, qaoa_ctx *b, double *f_out);
+
 /* Launch all further work of this context on an existing HIP stream
  * (hipStream_t passed as void*; NULL = the null stream).  The caller keeps
  * the stream alive while the context uses it. */

@@ -76,6 +76,7 @@ _SIGS = {
     "qaoa_cut_table": (_I, [_P, _P, _SZ]),
     "qaoa_get_state": (_I, [_P, _P, _SZ]),
     "qaoa_fidelity": (_I, [_P, _P, _DP]),
+    "qaoa_fidelity_noalloc": (_I, [_P, _P, _DP]),
     "qaoa_bind_stream": (_I, [_P, _P]),
     "qaoa_bind_state": (_I, [_P, _P, _SZ]),
     "qaoa_set_profiling": (_I, [_P, _I]),
@@ -218,6 +219,13 @@ def qaoa_get_state(ctx, n: int, prec="c128") -> np.ndarray:
 def qaoa_fidelity(a, b) -> float:
     f = ctypes.c_double()
     _err(_lib.qaoa_fidelity(a, b, ctypes.byref(f)))
+    return f.value
+
+
+def qaoa_fidelity_noalloc(a, b) -> float:
+    """qaoa_fidelity with the library's static device workspace (no allocation)."""
+    f = ctypes.c_double()
+    _err(_lib.qaoa_fidelity_noalloc(a, b, ctypes.byref(f)))
     return f.value
 
 

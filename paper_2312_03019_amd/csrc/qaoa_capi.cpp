@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "../../include/qaoa.h"
@@ -196,6 +197,86 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
     HIPCHK(launch_reverse(c->prec == QAOA_C64 ? 1 : 0, c->psi, (int64_t)1 << c->hg.n, c->stream));
     c->complemented = false;
   }
+  return QAOA_OK;
+}
+
+// Shared by qaoa_fidelity and qaoa_fidelity_noalloc: argument and state checks.
+int fidelity_check(qaoa_ctx* a, qaoa_ctx* b, double* f_out, const Busy& ba, const Busy& bb) {
+  if (!a || !b || !f_out || a == b) {
+    set_error("invalid arguments");
+    return QAOA_EINVAL;
+  }
+  if (!ba.ok || !bb.ok) {
+    set_error("context busy");
+    return QAOA_ESTATE;
+  }
+  if (a->hg.n != b->hg.n) {
+    set_error("qubit counts differ");
+    return QAOA_EINVAL;
+  }
+  if (!a->have_state || !b->have_state) {
+    set_error("both contexts need a state");
+    return QAOA_ESTATE;
+  }
+  if (a->device != b->device) {
+    set_error("the two contexts live on different devices");
+    return QAOA_EINVAL;
+  }
+  return QAOA_OK;
+}
+
+// The overlap sums of a and b in the device workspace d (fidelity_work(nb)
+// bytes), on a's stream after b's work; F = |<a|b>|^2 / (<a|a><b|b>).
+int fidelity_core(qaoa_ctx* a, qaoa_ctx* b, char* d, int nb, double* f_out) {
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int64_t N = (int64_t)1 << a->hg.n;
+  const int rev = a->complemented != b->complemented ? 1 : 0;
+  double h[4] = {0, 0, 0, 0};
+  hipError_t e = launch_fidelity_sums(a->prec, a->psi, b->prec, b->psi, N, rev, d, nb, a->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h, d + fidelity_work(nb).off_out, sizeof h, hipMemcpyDeviceToHost, a->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+  if (e != hipSuccess) {
+    set_error("fidelity: %s", hipGetErrorString(e));
+    return QAOA_EDEVICE;
+  }
+  *f_out = (h[0] * h[0] + h[1] * h[1]) / (h[2] * h[3]);
+  return QAOA_OK;
+}
+
+// Static device workspace of qaoa_fidelity_noalloc: one copy per GPU, held
+// until the process ends; every call on a GPU reuses it.  In host code the
+// array's name is only a stand-in for the symbol, so the device address is
+// looked up once per device (with that device current) and kept.
+constexpr size_t kScratchBytes = 66 * 1024;
+static __device__ __align__(256) char scratch[kScratchBytes];
+static_assert(sizeof(scratch) >= 4 * kFidelityMaxBlocks * sizeof(double) + 1024, "fidelity workspace must fit");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int device, char** out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device %d out of range", device);
+    return QAOA_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != device) HIPCHK(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) HIPCHK(hipSetDevice(cur));
+    HIPCHK(e);
+    if (!p) {
+      set_error("hipGetSymbolAddress returned NULL for the static workspace");
+      return QAOA_EDEVICE;
+    }
+    g_scratch_ptr[device] = (char*)p;
+  }
+  *out = g_scratch_ptr[device];
   return QAOA_OK;
 }
 
@@ -476,59 +557,30 @@ int qaoa_get_state(qaoa_ctx* c, void* host_out, size_t bytes) {
 }
 
 int qaoa_fidelity(qaoa_ctx* a, qaoa_ctx* b, double* f_out) {
-  if (!a || !b || !f_out || a == b) {
-    set_error("invalid arguments");
-    return QAOA_EINVAL;
-  }
   Busy ba(a), bb(b);
-  if (!ba.ok || !bb.ok) {
-    set_error("context busy");
-    return QAOA_ESTATE;
-  }
-  if (a->hg.n != b->hg.n) {
-    set_error("qubit counts differ");
+  int rc = fidelity_check(a, b, f_out, ba, bb);
+  if (rc) return rc;
+  const int nb = fidelity_blocks((int64_t)1 << a->hg.n);
+  char* d = nullptr;
+  HIPCHK(hipMalloc((void**)&d, fidelity_work(nb).bytes));
+  rc = fidelity_core(a, b, d, nb, f_out);
+  (void)hipFree(d);
+  return rc;
+}
+
+int qaoa_fidelity_noalloc(qaoa_ctx* a, qaoa_ctx* b, double* f_out) {
+  Busy ba(a), bb(b);
+  int rc = fidelity_check(a, b, f_out, ba, bb);
+  if (rc) return rc;
+  const int nb = fidelity_blocks((int64_t)1 << a->hg.n);
+  if (fidelity_work(nb).bytes > sizeof(scratch)) {
+    set_error("fidelity workspace of %zu bytes exceeds the %zu-byte static buffer", fidelity_work(nb).bytes,
+              sizeof(scratch));
     return QAOA_EINVAL;
   }
-  if (!a->have_state || !b->have_state) {
-    set_error("both contexts need a state");
-    return QAOA_ESTATE;
-  }
-  HIPCHK(hipStreamSynchronize(b->stream));
-  const int64_t N = (int64_t)1 << a->hg.n;
-  int nb = (int)std::min<int64_t>(2048, (N + 255) / 256);
-  // partials | jobs | spans | out
-  const size_t part_b = 4 * (size_t)nb * sizeof(double);
-  const size_t total = part_b + 4 * sizeof(ReduceJob) + 4 * sizeof(Span) + 4 * sizeof(double) + 256;
   char* d = nullptr;
-  HIPCHK(hipMalloc((void**)&d, total));
-  char* dj = d + part_b;
-  char* ds = dj + 4 * sizeof(ReduceJob);
-  double* dout = (double*)(ds + 4 * sizeof(Span));
-  ReduceJob jobs[4];
-  Span spans[4];
-  for (int k = 0; k < 4; ++k) {
-    memset(&jobs[k], 0, sizeof jobs[k]);
-    jobs[k].span_begin = k;
-    jobs[k].span_end = k + 1;
-    jobs[k].out = dout + k;
-    jobs[k].scale = 1.0;
-    spans[k] = Span{(const double*)d + (int64_t)k * nb, nb};
-  }
-  double h[4] = {0, 0, 0, 0};
-  hipError_t e = hipMemcpy(dj, jobs, sizeof jobs, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(ds, spans, sizeof spans, hipMemcpyHostToDevice);
-  const int rev = a->complemented != b->complemented ? 1 : 0;
-  if (e == hipSuccess) e = launch_overlap(a->prec, a->psi, b->prec, b->psi, N, (double*)d, nb, rev, a->stream);
-  if (e == hipSuccess) e = launch_reduce((const ReduceJob*)dj, (const Span*)ds, 4, a->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, a->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
-  (void)hipFree(d);
-  if (e != hipSuccess) {
-    set_error("fidelity: %s", hipGetErrorString(e));
-    return QAOA_EDEVICE;
-  }
-  *f_out = (h[0] * h[0] + h[1] * h[1]) / (h[2] * h[3]);
-  return QAOA_OK;
+  if ((rc = scratch_address(a->device, &d))) return rc;
+  return fidelity_core(a, b, d, nb, f_out);
 }
 
 int qaoa_bind_stream(qaoa_ctx* c, void* hip_stream) {

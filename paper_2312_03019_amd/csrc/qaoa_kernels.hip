@@ -875,6 +875,22 @@ __global__ void __launch_bounds__(256) k_overlap(const cx<Ra>* __restrict__ a, c
   }
 }
 
+// Reduce jobs for `njobs` equal rows of partials: job k sums part[k * count ..
+// (k + 1) * count) into out[k].  Filled on the device, so a caller needs no
+// host-to-device copy (and no host staging) before k_reduce.
+__global__ void k_row_jobs(ReduceJob* __restrict__ jobs, Span* __restrict__ spans, const double* part, int64_t count,
+                           int njobs, double* out) {
+  const int k = threadIdx.x;
+  if (k >= njobs) return;
+  ReduceJob j;
+  j.span_begin = k;
+  j.span_end = k + 1;
+  j.scale = 1.0;
+  j.out = out + k;
+  jobs[k] = j;
+  spans[k] = Span{part + (int64_t)k * count, count};
+}
+
 // Streaming copy: each thread moves four 16-byte vectors (all loads issued
 // before the stores), one workgroup per 16 KiB.
 __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s, float4* __restrict__ d, int64_t n) {
@@ -991,6 +1007,20 @@ hipError_t launch_cut_table(const GraphDev* g, bool weighted, void* out, int64_t
   if (weighted) hipLaunchKernelGGL(k_cut_table_f64, dim3(blocks), dim3(256), 0, st, g, (double*)out, N);
   else hipLaunchKernelGGL(k_cut_table_i32, dim3(blocks), dim3(256), 0, st, g, (int32_t*)out, N);
   return hipGetLastError();
+}
+
+hipError_t launch_fidelity_sums(int prec_a, const void* a, int prec_b, const void* b, int64_t N, int rev_b, char* work,
+                                int nblocks, hipStream_t st) {
+  const FidelityWork w = fidelity_work(nblocks);
+  double* part = (double*)(work + w.off_part);
+  ReduceJob* jobs = (ReduceJob*)(work + w.off_jobs);
+  Span* spans = (Span*)(work + w.off_spans);
+  double* out = (double*)(work + w.off_out);
+  hipError_t e = launch_overlap(prec_a, a, prec_b, b, N, part, nblocks, rev_b, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_jobs, dim3(1), dim3(64), 0, st, jobs, spans, (const double*)part, (int64_t)nblocks, 4, out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_reduce(jobs, spans, 4, st);
 }
 
 hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, int64_t N, double* part,

@@ -34,6 +34,31 @@ hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hi
 hipError_t launch_cut_table(const GraphDev* g, bool weighted, void* out, int64_t N, hipStream_t st);
 hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, int64_t N, double* part,
                           int nblocks, int rev_b, hipStream_t st);
+// Workspace of the fidelity sums, one device buffer: per-block partials
+// (4 rows of nblocks doubles), the reduce jobs and spans, and the four sums
+// Re<a|b>, Im<a|b>, <a|a>, <b|b> at off_out.  Sub-buffers are 256-byte aligned.
+struct FidelityWork {
+  size_t off_part, off_jobs, off_spans, off_out, bytes;
+};
+constexpr int kFidelityMaxBlocks = 2048;
+inline size_t round_up_256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline FidelityWork fidelity_work(int nblocks) {
+  FidelityWork w;
+  w.off_part = 0;
+  w.off_jobs = round_up_256(4 * (size_t)nblocks * sizeof(double));
+  w.off_spans = round_up_256(w.off_jobs + 4 * sizeof(ReduceJob));
+  w.off_out = round_up_256(w.off_spans + 4 * sizeof(Span));
+  w.bytes = round_up_256(w.off_out + 4 * sizeof(double));
+  return w;
+}
+inline int fidelity_blocks(int64_t N) {
+  const int64_t b = (N + 255) / 256;
+  return (int)(b < kFidelityMaxBlocks ? b : kFidelityMaxBlocks);
+}
+// Overlap partials, then the fixed-order reduction of each row, all in `work`
+// (fidelity_work(nblocks).bytes of device memory).
+hipError_t launch_fidelity_sums(int prec_a, const void* a, int prec_b, const void* b, int64_t N, int rev_b, char* work,
+                                int nblocks, hipStream_t st);
 // x[z] <-> x[N-1-z] in place (complements every index bit).
 hipError_t launch_reverse(int prec, void* x, int64_t N, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
