@@ -78,12 +78,21 @@ void qaoa_destroy(qaoa_ctx *ctx);
 int qaoa_max_qubits(int prec, int with_grad);
 
 /* Evolve |+>^n through p layers (p >= 0) with angles gamma[p], beta[p]
- * (finite doubles).  Enqueues work on the bound stream and returns; the
- * state stays on the device.  p = 0 leaves |+>^n. */
+ * (finite doubles): the circuit of Algorithm 1 (Section 2.1) with each
+ * level's RZZ gates compressed into one diagonal phase exp(-i gamma_l C(z))
+ * per basis state (Eq. UC_opt, Algorithm 2; launch control of Section 2.2
+ * for the start state), followed by exp(-i beta_l X) on every qubit.
+ * Enqueues work on the bound stream and returns; the state stays on the
+ * device.  p = 0 leaves |+>^n.  QAOA_EINVAL for p < 0, NULL angle arrays
+ * with p > 0 or a non-finite angle; QAOA_ENOMEM / QAOA_EDEVICE when the
+ * state cannot be allocated or a launch fails. */
 int qaoa_run(qaoa_ctx *ctx, int p, const double *gamma, const double *beta);
 
-/* <C> and the norm sum |psi|^2 of the last qaoa_run (both double; the norm
- * pointer may be NULL).  Synchronises the stream.  QAOA_ESTATE before any run. */
+/* <C> = sum_z |psi_z|^2 C(z), the expected cut the classical optimiser of
+ * the QAOA workflow (Section 1) consumes, and the norm sum |psi|^2, of the
+ * last qaoa_run or qaoa_run_gates (both double, accumulated in FP64 in a
+ * fixed order; the norm pointer may be NULL).  Synchronises the stream.
+ * QAOA_ESTATE before any run. */
 int qaoa_expect(qaoa_ctx *ctx, double *expect_out, double *norm_out);
 
 /* <C> and its gradient d<C>/dgamma_l, d<C>/dbeta_l for l < p, by one forward
@@ -129,12 +138,21 @@ int qaoa_sample(qaoa_ctx *ctx, int64_t count, const double *uniforms, uint64_t *
  * Weighted: double values (bytes = 8*2^n).  host_out is host memory. */
 int qaoa_cut_table(qaoa_ctx *ctx, void *host_out, size_t bytes);
 
-/* Copy the state of the last run to host memory: 2^n interleaved
- * (re, im) pairs of double (C128) or float (C64); bytes must match. */
+/* Copy the state of the last run (the 2^n amplitudes the paper's simulator
+ * evolves, Section 2.1; amplitude z at index z, qubit q = bit q of z) to
+ * host memory: 2^n interleaved (re, im) pairs of double (C128) or float
+ * (C64).  bytes must equal 2^n * 16 (C128) or 2^n * 8 (C64), else
+ * QAOA_EINVAL; QAOA_ESTATE without a state (no run, or after qaoa_grad).
+ * Synchronises the stream. */
 int qaoa_get_state(qaoa_ctx *ctx, void *host_out, size_t bytes);
 
 /* F = |<a|b>|^2 / (<a|a><b|b>) between the states of two contexts with the
- * same n (precisions may differ), accumulated in double on the device. */
+ * same n (precisions may differ), accumulated in double on the device: the
+ * agreement measure for the complex64 state against the complex128 one (the
+ * paper leaves its precision unstated, so both are offered).  QAOA_EINVAL
+ * for a == b, NULL pointers or different n; QAOA_ESTATE when a context has
+ * no state.  Allocates a device workspace of about 65 KiB for the call
+ * (qaoa_fidelity_noalloc does not).  Synchronises both streams. */
 int qaoa_fidelity(qaoa_ctx *a, qaoa_ctx *b, double *f_out);
 
 /* qaoa_fidelity for callers that cannot allocate device memory (code under
@@ -153,12 +171,17 @@ int qaoa_fidelity_noalloc(qaoa_ctx *a, qaoa_ctx *b, double *f_out);
 
 /* Launch all further work of this context on an existing HIP stream
  * (hipStream_t passed as void*; NULL = the null stream).  The caller keeps
- * the stream alive while the context uses it. */
+ * the stream alive while the context uses it.  Not a step of the paper's
+ * method: it lets the simulator share a caller's (e.g. torch's) stream.
+ * Synchronises the previous stream first. */
 int qaoa_bind_stream(qaoa_ctx *ctx, void *hip_stream);
 
-/* Use caller-owned device memory (e.g. a torch tensor) as the state vector.
+/* Use caller-owned device memory (e.g. a torch tensor) as the state vector
+ * (the 2^n-amplitude array of Section 2.1, in the layout of qaoa_get_state).
  * bytes must be exactly 2^n * (16 for C128, 8 for C64); dev_ptr must be
- * 256-byte aligned device memory that outlives the context's use of it. */
+ * 256-byte aligned device memory that outlives the context's use of it
+ * (borrowed, never freed), else QAOA_EINVAL.  After a run the buffer holds
+ * the final state in natural index order. */
 int qaoa_bind_state(qaoa_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Per-pass kernel timing of later runs: when enabled, every pass launch is

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qaoa_geometry.h"
 #include "qaoa_launch.h"
 #include "qaoa_plan.h"
 
@@ -29,23 +30,28 @@ struct V2<double> {
   typedef double T __attribute__((ext_vector_type(2)));
 };
 
-constexpr int kItems = 4;   // pairs (or amplitudes) per thread
+constexpr int kItems = kSweepItems;   // pairs (or amplitudes) per thread
 
 __device__ __forceinline__ int64_t insert_zero(int64_t i, int q) {
   return ((i >> q) << (q + 1)) | (i & ((int64_t(1) << q) - 1));
 }
 
+// The sweeps below run grid-stride over chunks of 256 * kItems items (the
+// grid is capped, see qaoa_geometry.h).
 template <typename R>
 __global__ void __launch_bounds__(256) k_gate_init(typename V2<R>::T* __restrict__ psi, int64_t N) {
-  const int64_t base = (int64_t)blockIdx.x * 256 * kItems + threadIdx.x;
+  const int64_t nchunks = sweep_chunks(N, 256 * kItems);
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t base = ch * 256 * kItems + threadIdx.x;
 #pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int64_t z = base + u * 256;
-    if (z < N) {
-      typename V2<R>::T v;
-      v.x = z == 0 ? (R)1 : (R)0;
-      v.y = (R)0;
-      psi[z] = v;
+    for (int u = 0; u < kItems; ++u) {
+      const int64_t z = base + u * 256;
+      if (z < N) {
+        typename V2<R>::T v;
+        v.x = z == 0 ? (R)1 : (R)0;
+        v.y = (R)0;
+        psi[z] = v;
+      }
     }
   }
 }
@@ -55,37 +61,40 @@ __global__ void __launch_bounds__(256) k_gate_init(typename V2<R>::T* __restrict
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_gate_pair(typename V2<R>::T* __restrict__ psi, int64_t half, int q, R c,
                                                    R s) {
-  const int64_t base = (int64_t)blockIdx.x * 256 * kItems + threadIdx.x;
   const int64_t bit = int64_t(1) << q;
-  typename V2<R>::T a[kItems], b[kItems];
+  const int64_t nchunks = sweep_chunks(half, 256 * kItems);
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t base = ch * 256 * kItems + threadIdx.x;
+    typename V2<R>::T a[kItems], b[kItems];
 #pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int64_t i = base + u * 256;
-    if (i < half) {
-      const int64_t z = insert_zero(i, q);
-      a[u] = psi[z];
-      b[u] = psi[z | bit];
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int64_t i = base + u * 256;
-    if (i < half) {
-      const int64_t z = insert_zero(i, q);
-      typename V2<R>::T x, y;
-      if (KIND == 0) {
-        x.x = (a[u].x + b[u].x) * c;
-        x.y = (a[u].y + b[u].y) * c;
-        y.x = (a[u].x - b[u].x) * c;
-        y.y = (a[u].y - b[u].y) * c;
-      } else {
-        x.x = c * a[u].x + s * b[u].y;
-        x.y = c * a[u].y - s * b[u].x;
-        y.x = c * b[u].x + s * a[u].y;
-        y.y = c * b[u].y - s * a[u].x;
+    for (int u = 0; u < kItems; ++u) {
+      const int64_t i = base + u * 256;
+      if (i < half) {
+        const int64_t z = insert_zero(i, q);
+        a[u] = psi[z];
+        b[u] = psi[z | bit];
       }
-      psi[z] = x;
-      psi[z | bit] = y;
+    }
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      const int64_t i = base + u * 256;
+      if (i < half) {
+        const int64_t z = insert_zero(i, q);
+        typename V2<R>::T x, y;
+        if (KIND == 0) {
+          x.x = (a[u].x + b[u].x) * c;
+          x.y = (a[u].y + b[u].y) * c;
+          y.x = (a[u].x - b[u].x) * c;
+          y.y = (a[u].y - b[u].y) * c;
+        } else {
+          x.x = c * a[u].x + s * b[u].y;
+          x.y = c * a[u].y - s * b[u].x;
+          y.x = c * b[u].x + s * a[u].y;
+          y.y = c * b[u].y - s * a[u].x;
+        }
+        psi[z] = x;
+        psi[z | bit] = y;
+      }
     }
   }
 }
@@ -94,16 +103,19 @@ __global__ void __launch_bounds__(256) k_gate_pair(typename V2<R>::T* __restrict
 template <typename R>
 __global__ void __launch_bounds__(256) k_gate_zz(typename V2<R>::T* __restrict__ psi, int64_t N, int u, int v, R pr,
                                                  R pi) {
-  const int64_t base = (int64_t)blockIdx.x * 256 * kItems + threadIdx.x;
+  const int64_t nchunks = sweep_chunks(N, 256 * kItems);
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t base = ch * 256 * kItems + threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t z = base + k * 256;
-    if (z < N && (((z >> u) ^ (z >> v)) & 1)) {
-      const typename V2<R>::T a = psi[z];
-      typename V2<R>::T r;
-      r.x = a.x * pr - a.y * pi;
-      r.y = a.x * pi + a.y * pr;
-      psi[z] = r;
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t z = base + k * 256;
+      if (z < N && (((z >> u) ^ (z >> v)) & 1)) {
+        const typename V2<R>::T a = psi[z];
+        typename V2<R>::T r;
+        r.x = a.x * pr - a.y * pi;
+        r.y = a.x * pi + a.y * pr;
+        psi[z] = r;
+      }
     }
   }
 }
@@ -358,8 +370,9 @@ hipError_t gate_run_t(const GateRun& r, hipStream_t st) {
   T* psi = (T*)r.psi;
   const int64_t N = int64_t(1) << r.n, half = N >> 1;
   const dim3 blk(256);
-  const dim3 gfull((unsigned)((N + 256 * kItems - 1) / (256 * kItems)));
-  const dim3 ghalf((unsigned)((half + 256 * kItems - 1) / (256 * kItems)));
+  const SweepGrids sg = sweep_grids(r.n);
+  const dim3 gfull((unsigned)sg.gate_full);
+  const dim3 ghalf((unsigned)sg.gate_half);
   hipLaunchKernelGGL(k_gate_init<R>, gfull, blk, 0, st, psi, N);
   const R h = (R)0.70710678118654752440;
   for (int q = 0; q < r.n; ++q) hipLaunchKernelGGL((k_gate_pair<R, 0>), ghalf, blk, 0, st, psi, half, q, h, (R)0);

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qaoa_geometry.h"
 #include "qaoa_plan.h"
 #include "qaoa_launch.h"
 
@@ -627,7 +628,10 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   if (!(flags & PF_NO_STORE)) store_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, ro0);
 }
 
-// Im sum over register pairs of conj(l_a) f_b + conj(l_b) f_a, for the qubits in mask.
+// Im sum over register pairs of conj(l_a) f_b + conj(l_b) f_a, for the qubits
+// in mask.  Each pair's four-product term is formed in the working precision
+// (like every other product of two amplitudes) and the sum over pairs and
+// qubits runs in FP64.
 template <typename R, int LOGR>
 __device__ __forceinline__ double dbeta_round(const cx<R> (&f)[1 << LOGR], const cx<R> (&l)[1 << LOGR],
                                               int mask, int cand = (1 << LOGR) - 1) {
@@ -636,18 +640,17 @@ __device__ __forceinline__ double dbeta_round(const cx<R> (&f)[1 << LOGR], const
 #pragma unroll
   for (int k = 0; k < LOGR; ++k) {
     if (!(((cand & mask) >> k) & 1)) continue;
-    R a = (R)0;
 #pragma unroll
     for (int j = 0; j < (1 << LOGR); ++j) {
       if (!(j & (1 << k))) {
         const int b = j | (1 << k);
-        a = fma(l[j].re, f[b].im, a);
+        R a = l[j].re * f[b].im;
         a = fma(-l[j].im, f[b].re, a);
         a = fma(l[b].re, f[j].im, a);
         a = fma(-l[b].im, f[j].re, a);
+        acc += (double)a;
       }
     }
-    acc += (double)a;
   }
   return acc;
 }
@@ -750,8 +753,9 @@ k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
           const int k = __builtin_ctz(ii);
           c0 += ((J >> k) & 1) ? sv.d[k] : -sv.d[k];
         }
-        const R im = l[J].re * f[J].im - l[J].im * f[J].re;   // Im(conj(l) f)
-        dG = fma(c0 + rt[J], (double)im, dG);
+        // Im(conj(l) f): products of two working-precision values are exact in FP64
+        const double im = fma((double)l[J].re, (double)f[J].im, -((double)l[J].im * (double)f[J].re));
+        dG = fma(c0 + rt[J], im, dG);
       }
       dG *= sg.bwg;
       if (!(nostore && s == 0)) {
@@ -1041,19 +1045,20 @@ hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, 
   return hipGetLastError();
 }
 
-// In-place reversal z <-> N-1-z (the complement of every index bit): thread
-// i < N/2 swaps one pair, so no element is read after another thread wrote it.
+// In-place reversal z <-> N-1-z (the complement of every index bit): item
+// i < N/2 swaps one pair, so no element is read after another thread wrote
+// it.  Grid-stride over items (the grid is capped, see qaoa_geometry.h).
 template <typename T>
 __global__ void __launch_bounds__(256) k_reverse(T* __restrict__ x, int64_t N) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N / 2) return;
-  const T a = x[i], b = x[N - 1 - i];
-  x[i] = b;
-  x[N - 1 - i] = a;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N / 2; i += (int64_t)gridDim.x * 256) {
+    const T a = x[i], b = x[N - 1 - i];
+    x[i] = b;
+    x[N - 1 - i] = a;
+  }
 }
 
 hipError_t launch_reverse(int prec, void* x, int64_t N, hipStream_t st) {
-  const int64_t blocks = (N / 2 + 255) / 256;
+  const int64_t blocks = N < 2 ? 0 : sweep_grids(63 - __builtin_clzll((unsigned long long)N)).reverse;
   if (blocks < 1) return hipSuccess;
   if (prec == 1) hipLaunchKernelGGL((k_reverse<float2>), dim3((unsigned)blocks), dim3(256), 0, st, (float2*)x, N);
   else hipLaunchKernelGGL((k_reverse<double2>), dim3((unsigned)blocks), dim3(256), 0, st, (double2*)x, N);
@@ -1069,7 +1074,7 @@ hipError_t launch_tile_cut(const GraphDev* g, int K, int nfree, const TileMap& m
 
 hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st) {
   const int64_t blocks = (n16 + 1023) / 1024;
-  if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (blocks < 1 || blocks * 256 > kMaxWorkItems) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src, (float4*)dst, n16);
   return hipGetLastError();
 }

@@ -83,7 +83,7 @@ def test_plan_covers_every_qubit_once(prec, kmax, pas, n):
         q.qaoa_destroy(h)
 
 
-def test_three_passes_per_layer_at_n30():
+def test_three_qubit_sets_two_passes_per_layer_at_n30():
     for prec in ("c64", "c128"):
         h = q.qaoa_create(30, [], None, prec)
         passes, sizes = q.qaoa_plan_info(h, 10)
