@@ -5,13 +5,19 @@ U[0,1) FP64 edge weights, p = 10 layers, gamma/beta uniform in [0, pi);
 the state starts at |+>^30 and the run ends with <C> on the host.
 One step = one full run (all HBM passes + the <C> reduction).
 
-value  = layer amplitude-updates per second, p * 2^n / t_step, complex64
-         state (the complex128 figure is reported beside it).
-roofline: the pass kernel, algorithmic bytes (one read + one write of the
-         state per pass, write-only for the first) / HIP-event kernel time.
-serve  : the serving workload (Poisson arrivals of mixed n in [14, 28],
-         p in [1, 12], 30% gradient requests, complex64, 200 GiB budget).
-cpu_baseline: the FP64 oracle on the host cores, on a bounded sample.
+value   : layer amplitude-updates per second, p * 2^n / t_step, complex64
+          state (the complex128 figure is reported beside it).
+roofline: the dominant pass kernel (largest share of the run's kernel time):
+          its algorithmic bytes per launch (one read + one write of the state,
+          write-only for the first pass) / its mean HIP-event launch time;
+          every pass kernel and every pass of the run are listed beside it.
+Other legs: the n = 26 precision comparison, a fresh context's time including
+the graph upload, adjoint gradients (n = 24 accuracy against the FP64 oracle
+and central differences; n = 28 HBM rates), the gate-by-gate circuit and the
+p-scan with the approximation ratio, optimised ratios, sampling, serving
+(Poisson arrivals of mixed n in [14, 28], p in [1, 12], 30% gradient
+requests, complex64, 200 GiB budget), and the FP64 oracle on the host cores
+on a bounded sample (cpu_baseline).
 """
 from __future__ import annotations
 
@@ -47,6 +53,9 @@ def parse():
     ap.add_argument("--no-gates", action="store_true")
     ap.add_argument("--no-optimize", action="store_true")
     ap.add_argument("--no-sample", action="store_true")
+    ap.add_argument("--no-n26", action="store_true")
+    ap.add_argument("--only-grad-hbm", action="store_true",
+                    help="run only the n=28 gradient leg and print its JSON (for profiling the adjoint sweep)")
     ap.add_argument("--profile-out", default=os.path.join(ROOT, "gpurun_out", "bench_passes.json"))
     return ap.parse_args()
 
@@ -73,33 +82,54 @@ def time_runs(q, torch, sim, g, b, steps, warmup):
     return t, e, nrm, np.array(ms_all), np.array(by_all)
 
 
-def pass_kinds(pass_ms):
-    """Mean kernel ms per kind of pass in the three-set schedule (high set
-    first, low set, high set with two layers' segments, ..., high set last):
-    the write-only first pass, the low-set passes, the merged high-set passes
-    and the last pass (with <C>)."""
-    ms = list(pass_ms)
-    if len(ms) < 3:
-        return {"all": ms}
-    mid = ms[1:-1]
-    return {"first": ms[0], "low_set": float(np.mean(mid[0::2])),
-            "high_set_merged": float(np.mean(mid[1::2])) if len(mid) > 1 else None, "last": ms[-1]}
+def pass_table(q, sim, pass_ms, pass_bytes):
+    """Every pass of the timed runs: qubit set, kernel, mean ms, GB/s and fraction of peak."""
+    rows = []
+    for i, (ms, by) in enumerate(zip(pass_ms, pass_bytes)):
+        st, name = q.qaoa_pass_kernel(sim.handle, i)
+        gbs = by / (ms * 1e-3) / 1e9
+        rows.append({"i": i, "set": st, "kernel": name, "ms": ms, "bytes": by, "gbps": gbs,
+                     "frac": gbs / HBM_PEAK_GBS})
+    return rows
 
 
-def pmc_traffic(path):
-    """Scaled HBM bytes per forward-pass launch from a committed rocprofv3
-    counter summary, or None when the kernel source changed since it was taken."""
+def kernel_table(rows):
+    """Per pass kernel: launches per run, mean ms, algorithmic bytes per launch,
+    GB/s, fraction of peak and share of the run's kernel time."""
+    tot = sum(r["ms"] for r in rows)
+    out = {}
+    for r in rows:
+        k = out.setdefault(r["kernel"], {"launches": 0, "ms_sum": 0.0, "bytes_sum": 0.0})
+        k["launches"] += 1
+        k["ms_sum"] += r["ms"]
+        k["bytes_sum"] += r["bytes"]
+    for name, k in out.items():
+        ms, by = k.pop("ms_sum"), k.pop("bytes_sum")
+        k["mean_ms"] = ms / k["launches"]
+        k["bytes_per_launch"] = by / k["launches"]
+        k["gbps"] = by / (ms * 1e-3) / 1e9
+        k["frac"] = k["gbps"] / HBM_PEAK_GBS
+        k["share"] = ms / tot
+    return out
+
+
+def pmc_traffic(path, kernel):
+    """Scaled HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
     import hashlib
     try:
         txt = open(path).read()
     except OSError:
         return None, "no counter summary"
-    fields = dict(re.findall(r"^- (\w+): (\S+)$", txt, re.M))
     src = os.path.join(ROOT, "paper_2312_03019_amd", "csrc", "qaoa_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
+    m = re.search(r"^- kernel_source_sha256: (\S+)$", txt, re.M)
+    if not m or m.group(1) != sha:
         return None, "kernel source changed since the counters were taken"
-    return float(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    m = re.search(r"^- traffic " + re.escape(kernel) + r": (\S+)$", txt, re.M)
+    if not m:
+        return None, f"no counters for {kernel}"
+    return float(m.group(1)), os.path.relpath(path, ROOT)
 
 
 def serve_bench(q, W, nreq):
@@ -147,31 +177,158 @@ def serve_bench(q, W, nreq):
     return out
 
 
+def _golden():
+    import json as _json
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")) as f:
+        return _json.load(f)
+
+
+def _err_stats(diffs, E):
+    a = np.abs(np.concatenate([np.ravel(d) for d in diffs])) / E
+    return {"max_over_E": float(a.max()), "median_over_E": float(np.median(a))}
+
+
 def grad_bench(q, torch, W):
-    """Adjoint gradients on the n=24 G(24, 0.3) p=8 workload, 64 parameter sets."""
+    """Adjoint gradients on the n=24 G(24, 0.3) p=8 workload, 64 parameter sets:
+    throughput, and the error of every one of the 16 partials of every set
+    against the stored FP64 oracle adjoint, against the stored FP64 oracle
+    central differences (h = 1e-6; the first four sets) and against central
+    differences of the complex128 device run (h = 1e-6; all 64 sets)."""
     prob, params = W.grad_gnp_n24()
+    gold = _golden()
+    ref = gold["grad_gnp_n24"]["sets"]
+    ref_fd = gold.get("grad_gnp_n24_fd", {}).get("sets", [])
+    E = float(prob.num_edges)
     out = {"workload": "n=24 G(24,0.3) unweighted (seed 4), p=8, 64 parameter sets U[0,pi); "
-                       "state 128/256 MiB (cache-resident, not an HBM roofline point)"}
+                       "state 128/256 MiB (cache-resident, not an HBM roofline point); errors are "
+                       "|d - d_ref| / |E| over all 16 partials of every set"}
+    grads = {}
     for prec in ("c64", "c128"):
         sim = q.Simulator(prob.n, prob.edges, None, prec)
         sim.grad(*params[0])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for g, b in params:
-            sim.grad(g, b)
+        res = [sim.grad(g, b) for g, b in params]
         t = time.perf_counter() - t0
+        grads[prec] = res
         q.qaoa_set_profiling(sim.handle, True)
         sim.grad(*params[0])
         ms, by = q.qaoa_pass_times(sim.handle)
         q.qaoa_set_profiling(sim.handle, False)
         passes, _ = sim.plan(len(params[0][0]))
         fm, fb, bm, bb = ms[:passes], by[:passes], ms[passes:], by[passes:]
+        d_or = [np.concatenate([r[1] - np.array(x["dgamma"]), r[2] - np.array(x["dbeta"])])
+                for r, x in zip(res, ref)]
+        d_fd = [np.concatenate([res[x["set"]][1] - np.array(x["dgamma"]), res[x["set"]][2] - np.array(x["dbeta"])])
+                for x in ref_fd]
         out[prec] = {"grads_per_s": len(params) / t, "ms_per_grad": 1e3 * t / len(params),
                      "forward_gbps": fb.sum() / (fm.sum() * 1e-3) / 1e9,
                      "backward_gbps": bb.sum() / (bm.sum() * 1e-3) / 1e9 if len(bm) else None,
-                     "forward_ms": float(fm.sum()), "backward_ms": float(bm.sum())}
+                     "forward_ms": float(fm.sum()), "backward_ms": float(bm.sum()),
+                     "err_vs_oracle_adjoint": _err_stats(d_or, E),
+                     "err_expect_vs_oracle_over_E": float(max(abs(r[0] - x["expect"]) for r, x in zip(res, ref)) / E)}
+        if d_fd:
+            out[prec]["err_vs_oracle_fd"] = dict(_err_stats(d_fd, E), sets=len(d_fd))
+        if prec == "c128":
+            # central differences of the complex128 device run, every set
+            h = 1e-6
+            diffs = []
+            for (g, b), r in zip(params, res):
+                fd = np.zeros(2 * len(g))
+                for l in range(len(g)):
+                    for k, (arr, other) in enumerate(((g, b), (b, g))):
+                        a1, a2 = arr.copy(), arr.copy()
+                        a1[l] += h
+                        a2[l] -= h
+                        e1 = sim.expect(a1, other)[0] if k == 0 else sim.expect(other, a1)[0]
+                        e2 = sim.expect(a2, other)[0] if k == 0 else sim.expect(other, a2)[0]
+                        fd[k * len(g) + l] = (e1 - e2) / (2 * h)
+                diffs.append((np.concatenate([r[1], r[2]]), fd))
+            out["c128"]["err_vs_device_c128_fd"] = _err_stats([a - f for a, f in diffs], E)
+            c64 = grads["c64"]
+            out["c64"]["err_vs_device_c128_fd"] = _err_stats(
+                [np.concatenate([x[1], x[2]]) - f for x, (_, f) in zip(c64, diffs)], E)
         sim.close()
     return out
+
+
+def grad_hbm_bench(q, torch, W, n=28, p=4, reps=3):
+    """Adjoint gradient at an HBM-bound size: n=28 weighted 3-regular, p=4
+    (2 GiB / 4 GiB per vector): per pass kernel of the forward and backward
+    sweeps, mean ms and algorithmic GB/s (backward passes move both vectors)."""
+    prob, g, b = W.weighted_3reg_n30(n=n, p=p)
+    out = {"workload": f"n={n} random 3-regular (seed 3) with U[0,1) weights, p={p}, gamma/beta U[0,pi); "
+                       f"bytes: forward 2*2^n*S per pass (+2^n*S for lam in the last), backward 4*2^n*S "
+                       f"(2*2^n*S for the pass undoing the first)"}
+    for prec in ("c64", "c128"):
+        sim = q.Simulator(prob.n, prob.edges, prob.weights, prec)
+        sim.grad(g, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sim.grad(g, b)
+        t = (time.perf_counter() - t0) / reps
+        q.qaoa_set_profiling(sim.handle, True)
+        sim.grad(g, b)
+        ms, by = q.qaoa_pass_times(sim.handle)
+        q.qaoa_set_profiling(sim.handle, False)
+        rows = pass_table(q, sim, ms, by)
+        passes, _ = sim.plan(p)
+        fwd, bwd = rows[:passes], rows[passes:]
+        out[prec] = {"ms_per_grad": t * 1e3, "forward_ms": float(sum(r["ms"] for r in fwd)),
+                     "backward_ms": float(sum(r["ms"] for r in bwd)),
+                     "backward_gbps": sum(r["bytes"] for r in bwd) / (sum(r["ms"] for r in bwd) * 1e-3) / 1e9,
+                     "kernels": kernel_table(rows)}
+        sim.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def n26_bench(q, torch, W, steps=5):
+    """The precision comparison workload: G(26, 0.5) unweighted, p=4, complex64
+    against complex128: time per run, speedup, <C> of each against the stored
+    FP64 oracle value, and 1 - fidelity between the two final states."""
+    prob, g, b = W.gnp_n26()
+    ref = _golden()["gnp_n26"]["expect"]
+    out = {"workload": "n=26 G(26,0.5) unweighted (seed 2), p=4, gamma/beta U[0,pi); states 512 MiB / 1 GiB"}
+    sims = {}
+    for prec in ("c64", "c128"):
+        sim = q.Simulator(prob.n, prob.edges, None, prec)
+        t, e, nrm, ms, by = time_runs(q, torch, sim, g, b, steps, 1)
+        out[prec] = {"ms_per_run": t * 1e3, "expect": e, "abs_err_vs_oracle_over_E": abs(e - ref) / prob.num_edges,
+                     "layer_amp_updates_per_s": len(g) * 2 ** prob.n / t}
+        sims[prec] = sim
+    out["c64_over_c128_speedup"] = out["c128"]["ms_per_run"] / out["c64"]["ms_per_run"]
+    out["one_minus_fidelity"] = 1.0 - sims["c64"].fidelity(sims["c128"])
+    for s_ in sims.values():
+        s_.close()
+    return out
+
+
+def upload_inclusive(q, torch, W, prob, g, b):
+    """A fresh context from qaoa_create to <C> on the host: graph validation and
+    upload, the per-set tile cut tables, the state allocation, the run image
+    upload and the run itself (the headline step excludes the first four)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim = q.Simulator(prob.n, prob.edges, prob.weights, "c64")
+    e, _ = sim.expect(g, b)
+    t = time.perf_counter() - t0
+    sim.close()
+    torch.cuda.empty_cache()
+    return {"ms": t * 1e3, "expect": e,
+            "note": "complex64, fresh context: create + graph upload + tile cut tables + state allocation + run + <C>"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def _time(torch, fn, reps):
@@ -196,6 +353,7 @@ def gates_bench(q, torch, W, prob, g, b):
     t_gate = {p: _time(torch, lambda p=p: (sim.run_gates(gg[:p], bb[:p]), q.qaoa_expect(sim.handle)), 2)
               for p in (1, 2, 3)}
     t_fused = {p: _time(torch, lambda p=p: sim.expect(gg[:p], bb[:p]), 3) for p in range(1, 21)}
+    e_fused = {p: sim.expect(gg[:p], bb[:p])[0] for p in range(1, 21)}
     v, _ = sim.max_cut()
     sim.close()
     base = t_gate[1]
@@ -206,6 +364,9 @@ def gates_bench(q, torch, W, prob, g, b):
         "fused_over_gate_p1": {p: t / base for p, t in t_fused.items()},
         "gate_over_gate_p1": {p: t / base for p, t in t_gate.items()},
         "max_cut": v,
+        "expect": e_fused,
+        "approx_ratio": {p: e / v for p, e in e_fused.items()},
+        "ratio_note": "<C>/max C at the scan's seeded angles (not optimised)",
     }
     # complete graphs K_N, N = 21..30, p = 5, unweighted: the configuration of the
     # paper's timing tables, here both circuits on the same device
@@ -280,17 +441,17 @@ def sample_bench(q, torch, W, prob, g, b, count=1 << 20):
             "note": "uniforms from numpy default_rng(80); time includes the CDF pass over the 8 GiB state"}
 
 
-def copy_ceiling(q, torch, nbytes=4 << 30, reps=5):
+def copy_ceiling(q, torch, nbytes=4 << 30, reps=5, block_bytes=16384):
     """Device-to-device streaming copy with the library's probe kernel (GB/s, read + write)."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     st = torch.cuda.current_stream()
-    q.qaoa_copy_probe(src, dst, nbytes, st)
+    q.qaoa_copy_probe(src, dst, nbytes, st, block_bytes)
     st.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(st)
     for _ in range(reps):
-        q.qaoa_copy_probe(src, dst, nbytes, st)
+        q.qaoa_copy_probe(src, dst, nbytes, st, block_bytes)
     b.record(st)
     b.synchronize()
     ms = a.elapsed_time(b) / reps
@@ -305,7 +466,7 @@ def cpu_baseline(W, prob, g, b, layers=2):
     oracle.run_expect(prob.n, prob.edges, prob.weights, g[:layers], b[:layers])
     dt = time.perf_counter() - t0
     return {"value": layers * (2 ** prob.n) / dt, "unit": "layer amp-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"FP64 oracle on the same n={prob.n} graph, the first {layers} of the {len(g)} layers "
                       f"(same angles) plus <C>: {dt:.1f} s; value = {layers} * 2^{prob.n} / t"}
 
@@ -320,6 +481,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if a.only_grad_hbm:
+        print(json.dumps({"grad_hbm": grad_hbm_bench(q, torch, W)}), flush=True)
+        return
     prob, g, b = W.weighted_3reg_n30(n=a.n, p=a.p)
     stream = torch.cuda.current_stream()
     res = {}
@@ -327,9 +491,11 @@ def main():
         sim = q.Simulator(prob.n, prob.edges, prob.weights, prec, stream=stream)
         t, e, nrm, ms, by = time_runs(q, torch, sim, g, b, a.steps, a.warmup)
         passes, sizes = sim.plan(a.p)
-        res[prec] = {"t": t, "expect": e, "norm": nrm, "pass_ms": ms.mean(axis=0).tolist(),
-                     "pass_ms_all": ms.tolist(), "pass_bytes": by[0].tolist(), "passes": passes, "sets": sizes,
+        rows = pass_table(q, sim, ms.mean(axis=0), by[0])
+        res[prec] = {"t": t, "expect": e, "norm": nrm, "passes": passes, "sets": sizes, "rows": rows,
+                     "kernels": kernel_table(rows), "pass_ms_all": ms.tolist(),
                      "launch_ms_mean": float(ms.mean()), "launch_bytes_mean": float(by.mean())}
+        print(f"[bench] n={a.n} p={a.p} {prec}: {t * 1e3:.2f} ms per run", file=sys.stderr, flush=True)
         if prec == "c64":
             keep64 = sim
         else:
@@ -338,11 +504,14 @@ def main():
     del keep64
     torch.cuda.empty_cache()
 
-    copy_gbs = copy_ceiling(q, torch)
+    copy16 = copy_ceiling(q, torch, block_bytes=16384)
+    copy4 = copy_ceiling(q, torch, block_bytes=4096)
     torch.cuda.empty_cache()
     r64 = res["c64"]
-    # algorithmic bytes per launch / mean launch duration, over every forward-pass launch of the timed runs
-    achieved = r64["launch_bytes_mean"] / (r64["launch_ms_mean"] * 1e-3) / 1e9
+    kern = r64["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["share"])     # the kernel with the largest share of kernel time
+    dk = kern[dom]
+    achieved = dk["gbps"]
     line = {
         "metric": METRIC,
         "value": a.p * 2 ** a.n / r64["t"],
@@ -354,34 +523,48 @@ def main():
         "config": {"workload": f"n={a.n} random 3-regular (seed 3) with U[0,1) FP64 weights, p={a.p}, "
                                f"gamma/beta U[0,pi), complex64 state, |+>^n start, <C> to host",
                    "passes_per_run": r64["passes"], "qubit_sets": r64["sets"]},
-        "hbm_gbps": achieved,
+        "hbm_gbps_all_passes": r64["launch_bytes_mean"] / (r64["launch_ms_mean"] * 1e-3) / 1e9,
         "expect_c64": r64["expect"],
     }
     if "c128" in res:
         r128 = res["c128"]
         line["c128"] = {"value": a.p * 2 ** a.n / r128["t"], "ms_per_step": r128["t"] * 1e3,
-                        "hbm_gbps": r128["launch_bytes_mean"] / (r128["launch_ms_mean"] * 1e-3) / 1e9,
-                        "expect": r128["expect"]}
+                        "hbm_gbps_all_passes": r128["launch_bytes_mean"] / (r128["launch_ms_mean"] * 1e-3) / 1e9,
+                        "expect": r128["expect"], "kernels": r128["kernels"],
+                        "passes": [{k: r[k] for k in ("i", "set", "kernel", "ms", "gbps", "frac")} for r in r128["rows"]]}
         line["c64_over_c128_speedup"] = r128["t"] / r64["t"]
         line["delta_expect_c64_c128"] = r64["expect"] - r128["expect"]
         line["one_minus_fidelity_c64_c128"] = 1.0 - res["fidelity_c64_c128"]
     traffic, tsrc = (None, "counters apply to the n=30 p=10 workload only")
     if a.n == 30 and a.p == 10:
-        traffic, tsrc = pmc_traffic(os.path.join(ROOT, "profiles", "k_fwd_weighted3reg_n30_p10_c64_counters.md"))
+        traffic, tsrc = pmc_traffic(os.path.join(ROOT, "profiles", "pass_kernels_weighted3reg_n30_p10_counters.md"),
+                                    dom)
     line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS,
                         "traffic": None if traffic is None else traffic / 1e9,
                         "traffic_unit": "GB per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-kernel scaled)",
                         "traffic_source": tsrc,
-                        "kernel": "k_fwd (one launch per HBM pass, all shapes)",
-                        "launches_timed": a.steps * r64["passes"],
-                        "algorithmic_bytes_per_launch": r64["launch_bytes_mean"],
-                        "mean_launch_ms": r64["launch_ms_mean"],
-                        "copy_ceiling_gbps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                        "pass_ms_by_kind": pass_kinds(r64["pass_ms"]) if len(r64["sets"]) == 3 else None,
-                        "per_launch_bytes": "2*2^n*8 read+write (write-only 2^n*8 for the first pass)"}
+                        "kernel": dom,
+                        "kernel_share_of_run": dk["share"],
+                        "launches_timed": a.steps * dk["launches"],
+                        "algorithmic_bytes_per_launch": dk["bytes_per_launch"],
+                        "mean_launch_ms": dk["mean_ms"],
+                        "per_launch_bytes": "2*2^n*8 read+write (write-only 2^n*8 for the first pass)",
+                        "copy_ceiling_gbps_16k_per_wg": copy16, "copy_ceiling_gbps_4k_per_wg": copy4,
+                        "frac_of_copy_4k": achieved / copy4,
+                        "kernels": kern,
+                        "passes": [{k: r[k] for k in ("i", "set", "kernel", "ms", "gbps", "frac")} for r in r64["rows"]],
+                        "all_passes_gbps": line["hbm_gbps_all_passes"]}
+    if a.n == 30 and a.p == 10:
+        line["t_including_upload"] = upload_inclusive(q, torch, W, prob, g, b)
+    if not a.no_n26:
+        line["n26"] = n26_bench(q, torch, W)
+        print("[bench] n26 done", file=sys.stderr, flush=True)
     if not a.no_grad:
         line["grad"] = grad_bench(q, torch, W)
+        print("[bench] grad n24 done", file=sys.stderr, flush=True)
+        line["grad_hbm"] = grad_hbm_bench(q, torch, W)
+        print("[bench] grad n28 done", file=sys.stderr, flush=True)
     if not a.no_gates:
         line["gates"] = gates_bench(q, torch, W, prob, g, b)
     if not a.no_optimize:
@@ -390,6 +573,7 @@ def main():
         line["sample"] = sample_bench(q, torch, W, prob, g, b)
     if not a.no_serve:
         line["serve"] = serve_bench(q, W, a.serve_requests)
+        print("[bench] serve done", file=sys.stderr, flush=True)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(W, prob, g, b)
     os.makedirs(os.path.dirname(a.profile_out), exist_ok=True)

@@ -196,6 +196,13 @@ int qaoa_set_profiling(qaoa_ctx *ctx, int enable);
  * stream.  Only runs made while profiling is enabled are timed. */
 int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count);
 
+/* Measurement hook: pass `index` of the last run (forward passes in launch
+ * order, then after qaoa_grad the backward passes), the qubit set it mixes
+ * (0 = the low set) and the name of the kernel it ran, as the profiler
+ * reports it without the parameter list (NUL-terminated, truncated to len).
+ * QAOA_EINVAL for an index outside the last run. */
+int qaoa_pass_kernel(qaoa_ctx *ctx, int index, int *set_out, char *name, size_t len);
+
 /* Plan of a run of depth p: number of HBM passes, number of qubit sets the
  * mixer is split into, and the qubits per set (sizes[] up to max_sets). */
 int qaoa_plan_info(qaoa_ctx *ctx, int p, int *passes, int *sets, int *sizes, int max_sets);
@@ -211,9 +218,11 @@ int qaoa_plan_info(qaoa_ctx *ctx, int p, int *passes, int *sets, int *sizes, int
 int qaoa_tile_map(int n, int prec, int set, int *k_out, int8_t *tpos, int8_t *gpos, uint64_t *gmask,
                   int8_t *gshift);
 
-/* Bandwidth reference: copy bytes (a multiple of 16) from src to dst, both
- * device pointers, with a plain streaming kernel on the given stream. */
-int qaoa_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
+/* Bandwidth reference (not a step of the method): copy bytes (a multiple of
+ * 16) from src to dst, both device pointers, with a plain streaming kernel
+ * on the given stream; block_bytes = 4096 or 16384 bytes per workgroup
+ * (one or four 16-byte vectors per thread), else QAOA_EINVAL. */
+int qaoa_copy_probe(const void *src, void *dst, size_t bytes, int block_bytes, void *hip_stream);
 
 /* Thread-local message describing the last failure on this thread. */
 const char *qaoa_last_error(void);

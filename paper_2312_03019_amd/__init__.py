@@ -81,10 +81,11 @@ _SIGS = {
     "qaoa_bind_state": (_I, [_P, _P, _SZ]),
     "qaoa_set_profiling": (_I, [_P, _I]),
     "qaoa_pass_times": (_I, [_P, ctypes.POINTER(ctypes.c_float), _DP, _I, ctypes.POINTER(_I)]),
+    "qaoa_pass_kernel": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.c_char_p, _SZ]),
     "qaoa_plan_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I), _I]),
     "qaoa_tile_map": (_I, [_I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(ctypes.c_int8),
                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int8)]),
-    "qaoa_copy_probe": (_I, [_P, _P, _SZ, _P]),
+    "qaoa_copy_probe": (_I, [_P, _P, _SZ, _I, _P]),
     "qaoa_last_error": (ctypes.c_char_p, []),
     "qaoa_serve_create": (_I, [_SZ, _I, _I, ctypes.POINTER(_P)]),
     "qaoa_serve_submit": (_I, [_P, ctypes.POINTER(qaoa_request), _D, ctypes.POINTER(ctypes.c_uint64)]),
@@ -257,6 +258,14 @@ def qaoa_pass_times(ctx, max_passes: int = 4096):
     return np.array(ms[:k], dtype=np.float64), np.array(by[:k], dtype=np.float64)
 
 
+def qaoa_pass_kernel(ctx, index: int):
+    """(qubit set, kernel name) of pass `index` of the last run."""
+    st = ctypes.c_int()
+    buf = ctypes.create_string_buffer(160)
+    _err(_lib.qaoa_pass_kernel(ctx, int(index), ctypes.byref(st), buf, 160))
+    return st.value, buf.value.decode()
+
+
 def qaoa_plan_info(ctx, p: int):
     passes, sets = ctypes.c_int(), ctypes.c_int()
     sizes = (ctypes.c_int * 64)()
@@ -278,12 +287,12 @@ def qaoa_tile_map(n: int, prec: str, set_index: int):
             np.array(gm[:], dtype=np.uint64), np.array(gs[:], dtype=np.int64))
 
 
-def qaoa_copy_probe(src, dst, nbytes: int, stream=None) -> None:
+def qaoa_copy_probe(src, dst, nbytes: int, stream=None, block_bytes: int = 16384) -> None:
     if hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
     s = src.data_ptr() if hasattr(src, "data_ptr") else src
     d = dst.data_ptr() if hasattr(dst, "data_ptr") else dst
-    _err(_lib.qaoa_copy_probe(ctypes.c_void_p(s), ctypes.c_void_p(d), int(nbytes),
+    _err(_lib.qaoa_copy_probe(ctypes.c_void_p(s), ctypes.c_void_p(d), int(nbytes), int(block_bytes),
                               ctypes.c_void_p(stream) if stream else None))
 
 

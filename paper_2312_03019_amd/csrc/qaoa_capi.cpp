@@ -57,6 +57,8 @@ struct qaoa_ctx {
   std::vector<hipEvent_t> ev;
   int ntimed = 0;
   std::vector<double> pass_bytes;
+  std::vector<int> pass_set, pass_shape;   // per pass of the last run (forward, then backward)
+  int pass_logr = 0, pass_nfwd = 0;
   std::atomic<int> busy{0};
 };
 
@@ -182,6 +184,13 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
   c->ntimed = c->profiling ? (int)(nf + nb) : 0;
   c->pass_bytes = img.pass_bytes;
   c->pass_bytes.insert(c->pass_bytes.end(), img.bwd_bytes.begin(), img.bwd_bytes.end());
+  c->pass_set = img.fwd_set;
+  c->pass_set.insert(c->pass_set.end(), img.bwd_set.begin(), img.bwd_set.end());
+  c->pass_shape.clear();
+  for (const PassDesc& d : img.fwd) c->pass_shape.push_back(d.shape);
+  for (const PassDesc& d : img.bwd) c->pass_shape.push_back(d.shape);
+  c->pass_logr = logr;
+  c->pass_nfwd = (int)nf;
   const PassDesc* dbwd = (const PassDesc*)(c->dev_img + lay.off_bwd);
   for (size_t i = 0; i < nb; ++i) {
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * (nf + i)], c->stream));
@@ -396,6 +405,8 @@ int qaoa_run_gates(qaoa_ctx* c, int p, const double* gamma, const double* beta) 
   HIPCHK(hipMemcpyAsync(c->host_out, c->dev_out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   c->complemented = false;
   c->ntimed = 0;
+  c->pass_shape.clear();
+  c->pass_set.clear();
   c->have_state = c->have_expect = true;
   return QAOA_OK;
 }
@@ -644,6 +655,23 @@ int qaoa_pass_times(qaoa_ctx* c, float* ms, double* bytes, int max, int* count) 
   return QAOA_OK;
 }
 
+int qaoa_pass_kernel(qaoa_ctx* c, int index, int* set_out, char* name, size_t len) {
+  Busy b(c);
+  if (!b.ok) {
+    set_error(c ? "context busy" : "context is NULL");
+    return c ? QAOA_ESTATE : QAOA_EINVAL;
+  }
+  if (index < 0 || index >= (int)c->pass_shape.size()) {
+    set_error("the last run has %d passes", (int)c->pass_shape.size());
+    return QAOA_EINVAL;
+  }
+  if (set_out) *set_out = c->pass_set[index];
+  if (name && len > 0)
+    pass_kernel_name(c->prec == QAOA_C64 ? 1 : 0, index >= c->pass_nfwd, c->pass_logr, c->pass_shape[index], name,
+                     len);
+  return QAOA_OK;
+}
+
 int qaoa_plan_info(qaoa_ctx* c, int p, int* passes, int* sets, int* sizes, int max_sets) {
   if (!c || p < 0) {
     set_error("invalid arguments");
@@ -679,12 +707,12 @@ int qaoa_tile_map(int n, int prec, int set, int* k_out, int8_t* tpos, int8_t* gp
   return QAOA_OK;
 }
 
-int qaoa_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
-  if (!src || !dst || bytes == 0 || bytes % 16) {
-    set_error("copy probe needs non-NULL pointers and a multiple of 16 bytes");
+int qaoa_copy_probe(const void* src, void* dst, size_t bytes, int block_bytes, void* hip_stream) {
+  if (!src || !dst || bytes == 0 || bytes % 16 || (block_bytes != 4096 && block_bytes != 16384)) {
+    set_error("copy probe needs non-NULL pointers, a multiple of 16 bytes and 4096 or 16384 bytes per workgroup");
     return QAOA_EINVAL;
   }
-  HIPCHK(launch_copy(src, dst, (int64_t)(bytes / 16), (hipStream_t)hip_stream));
+  HIPCHK(launch_copy(src, dst, (int64_t)(bytes / 16), block_bytes, (hipStream_t)hip_stream));
   return QAOA_OK;
 }
 

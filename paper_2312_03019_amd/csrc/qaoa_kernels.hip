@@ -25,6 +25,7 @@
 // phase is then a product tree of 1 + LOGR complex exponentials.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
 
 #include "qaoa_geometry.h"
 #include "qaoa_plan.h"
@@ -174,26 +175,34 @@ __device__ __forceinline__ void transpose(cx<R>* lds, cx<R> (&v)[1 << LOGR], uin
 // least one tile bit s (the highest shared one is used), so the tile splits
 // into the two halves s = 0 / s = 1 that move one after the other through
 // half the LDS (index with bit s removed).  Three workgroups then share a CU
-// (the register budget of three waves per SIMD) instead of two.  The swizzles
-// below spread the lanes of every such access over distinct banks: each index
-// bit above the bank group XORs a chosen pattern into the bank bits
-// (GF(2)-linear, hence a bijection).  Complex64: 32 lanes x 8 B per bank
-// cycle, 5 bank bits; complex128: 16 lanes x 16 B, 4 bank bits.  Both were
-// checked against every access of every round transition of the tile shape
-// (the complex128 pattern was found by a search over such patterns).
+// (the register budget of three waves per SIMD) instead of two.
+//
+// Bank model (gfx950, 64 banks of 4 bytes): an LDS access of 8 or 16 bytes
+// per lane is served in groups of lanes, and the lanes of a group conflict
+// when their byte ranges share a bank.  The counters show the groups are
+// 128 bytes wide for some accesses (16 lanes x 8 B, 8 lanes x 16 B) and the
+// swizzles are built to be conflict-free for 256-byte groups (32 x 8 B,
+// 16 x 16 B) as well.  The swizzle XORs into the bank bits of the LDS index
+// a GF(2)-linear function of its higher bits, each bit flipping only bits
+// below itself (triangular, hence a bijection).  The patterns were found by
+// a search over such functions and checked for every access of every round
+// transition of the tile shape (tests/test_lds_swizzle.py repeats the check).
 template <typename R>
 __device__ __forceinline__ uint32_t swz_half(uint32_t c);
 template <>
 __device__ __forceinline__ uint32_t swz_half<float>(uint32_t c) {
-  const uint32_t f = ((c >> 5) & 7u) ^ (((c >> 8) & 1u) * 24u) ^ (((c >> 9) & 1u) << 4) ^ ((c >> 10) & 3u);
+  constexpr uint32_t P[8] = {1u, 2u, 6u, 11u, 16u, 0u, 16u, 0u};   // for index bits 4..11
+  uint32_t f = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) f ^= ((c >> (4 + i)) & 1u) * P[i];
   return c ^ f;
 }
 template <>
 __device__ __forceinline__ uint32_t swz_half<double>(uint32_t c) {
-  constexpr uint32_t P[7] = {3u, 10u, 13u, 6u, 9u, 9u, 15u};   // for index bits 4..10
+  constexpr uint32_t P[8] = {1u, 3u, 6u, 8u, 1u, 0u, 0u, 0u};      // for index bits 3..10
   uint32_t f = 0;
 #pragma unroll
-  for (int i = 0; i < 7; ++i) f ^= ((c >> (4 + i)) & 1u) * P[i];
+  for (int i = 0; i < 8; ++i) f ^= ((c >> (3 + i)) & 1u) * P[i];
   return c ^ f;
 }
 __device__ __forceinline__ uint32_t drop_bit(uint32_t x, int s) {
@@ -895,16 +904,20 @@ __global__ void k_row_jobs(ReduceJob* __restrict__ jobs, Span* __restrict__ span
   spans[k] = Span{part + (int64_t)k * count, count};
 }
 
-// Streaming copy: each thread moves four 16-byte vectors (all loads issued
-// before the stores), one workgroup per 16 KiB.
-__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s, float4* __restrict__ d, int64_t n) {
-  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  float4 x[4];
+// Streaming copy through the global address space: each thread moves ITEMS
+// 16-byte vectors (all loads issued before the stores), one workgroup per
+// 256 * ITEMS * 16 bytes (4 KiB for ITEMS = 1, 16 KiB for ITEMS = 4).
+template <int ITEMS>
+__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s_, float4* __restrict__ d_, int64_t n) {
+  const QGLOBAL float4* s = (const QGLOBAL float4*)s_;
+  QGLOBAL float4* d = (QGLOBAL float4*)d_;
+  const int64_t base = (int64_t)blockIdx.x * (256 * ITEMS) + threadIdx.x;
+  float4 x[ITEMS];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < ITEMS; ++u)
     if (base + u * 256 < n) x[u] = s[base + u * 256];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < ITEMS; ++u)
     if (base + u * 256 < n) d[base + u * 256] = x[u];
 }
 
@@ -999,6 +1012,39 @@ hipError_t launch_pass(int prec, bool backward, int logr, int shape, const PassD
   return launch_pass_t<double, kTileBitsC128>(backward, logr, shape, d, ndesc, nblocks, nthreads, st);
 }
 
+// Mirrors the specialisations launch_pass_t selects (same cases, same
+// template arguments); anything else is the generic kernel.
+void pass_kernel_name(int prec, bool backward, int logr, int shape, char* buf, size_t len) {
+  const char* R = prec == 1 ? "float" : "double";
+  const int KB = prec == 1 ? kTileBitsC64 : kTileBitsC128;
+  const int LMAX = prec == 1 ? kLogRC64 : kLogRC128;
+  const int nrc = shape >> 3, code = shape & 7;
+  if (backward) {
+    bool shaped = logr == LMAX && ((code == kShapeFirst && nrc >= 1 && nrc <= 3) ||
+                                   (code == kShapeSingle && nrc >= 1 && nrc <= 4) ||
+                                   (code == kShapeMerged && nrc >= 1 && nrc <= 3));
+    if (shaped) {
+      const int nsc = code == kShapeMerged ? 2 : 1, phm = code == kShapeFirst ? 1 : code == kShapeMerged ? 2 : 0;
+      snprintf(buf, len, "k_bwd<%s, %d, %d, %d, %d, %d, %d>", R, LMAX, KB, nrc, nsc, phm, code == kShapeFirst ? 1 : 0);
+    } else {
+      snprintf(buf, len, "k_bwd<%s, %d, %d, 0, 0, -1, -1>", R, logr, KB);
+    }
+    return;
+  }
+  bool shaped = logr == LMAX && (((code == kShapeFirst || code == kShapeLast || code == kShapeLastLam) && nrc >= 1 &&
+                                  nrc <= 4) ||
+                                 ((code == kShapeSingle || code == kShapeMerged) && nrc >= 1 && nrc <= 3));
+  if (!shaped) {
+    snprintf(buf, len, "k_fwd<%s, %d, %d, 0, 0, -1, -1, -1, 0>", R, logr, KB);
+    return;
+  }
+  const int nsc = code == kShapeMerged ? 2 : 1;
+  const int phm = code == kShapeFirst ? 1 : code == kShapeMerged ? 2 : 0;
+  const int gen = code == kShapeFirst ? 1 : 0;
+  const int exp = code == kShapeLast ? 1 : code == kShapeLastLam ? 2 : 0;
+  snprintf(buf, len, "k_fwd<%s, %d, %d, %d, %d, %d, %d, %d, 1>", R, LMAX, KB, nrc, nsc, phm, gen, exp);
+}
+
 hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce, dim3(njobs), dim3(256), 0, st, jobs, spans);
@@ -1072,10 +1118,15 @@ hipError_t launch_tile_cut(const GraphDev* g, int K, int nfree, const TileMap& m
   return hipGetLastError();
 }
 
-hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st) {
-  const int64_t blocks = (n16 + 1023) / 1024;
+hipError_t launch_copy(const void* src, void* dst, int64_t n16, int block_bytes, hipStream_t st) {
+  const int items = block_bytes / (256 * 16);
+  if (items != 1 && items != 4) return hipErrorInvalidValue;
+  const int64_t blocks = (n16 + 256 * items - 1) / (256 * items);
   if (blocks < 1 || blocks * 256 > kMaxWorkItems) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src, (float4*)dst, n16);
+  if (items == 1)
+    hipLaunchKernelGGL(k_copy<1>, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src, (float4*)dst, n16);
+  else
+    hipLaunchKernelGGL(k_copy<4>, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src, (float4*)dst, n16);
   return hipGetLastError();
 }
 

@@ -30,6 +30,9 @@ enum : int {
 // share logr and (forward) shape.
 hipError_t launch_pass(int prec, bool backward, int logr, int shape, const PassDesc* d, int ndesc, int64_t nblocks,
                        int nthreads, hipStream_t st);
+// Name of the kernel launch_pass runs for these arguments, as the profiler
+// reports it without the parameter list (e.g. "k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>").
+void pass_kernel_name(int prec, bool backward, int logr, int shape, char* buf, size_t len);
 hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hipStream_t st);
 hipError_t launch_cut_table(const GraphDev* g, bool weighted, void* out, int64_t N, hipStream_t st);
 hipError_t launch_overlap(int prec_a, const void* a, int prec_b, const void* b, int64_t N, double* part,
@@ -61,7 +64,8 @@ hipError_t launch_fidelity_sums(int prec_a, const void* a, int prec_b, const voi
                                 int nblocks, hipStream_t st);
 // x[z] <-> x[N-1-z] in place (complements every index bit).
 hipError_t launch_reverse(int prec, void* x, int64_t N, hipStream_t st);
-hipError_t launch_copy(const void* src, void* dst, int64_t n16, hipStream_t st);
+// block_bytes: bytes per workgroup, 4096 or 16384.
+hipError_t launch_copy(const void* src, void* dst, int64_t n16, int block_bytes, hipStream_t st);
 // Per-tile cut table (kTileCutStride doubles per tile) of one qubit set.
 hipError_t launch_tile_cut(const GraphDev* g, int K, int nfree, const TileMap& map, int64_t ntiles, double* out,
                            hipStream_t st);

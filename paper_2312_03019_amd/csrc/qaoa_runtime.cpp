@@ -493,6 +493,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
     }
     d.tile_begin = 0;
     img->fwd.push_back(d);
+    img->fwd_set.push_back(ps.set);
     double by = ps.gen ? state_bytes : 2.0 * state_bytes;
     if (ps.expect && rq.grad) by += state_bytes;
     img->pass_bytes.push_back(by);
@@ -507,6 +508,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
       b.part = (double*)(intptr_t)part;
       part += 2 * (int64_t)d.nseg * ntiles;
       img->bwd.push_back(b);
+      img->bwd_set.push_back(ps.set);
       img->bwd_bytes.push_back(ps.gen ? 2.0 * state_bytes : 4.0 * state_bytes);   // phi and lam
     }
   }
@@ -548,6 +550,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
   // backward launches run from the last forward pass to the first
   std::reverse(img->bwd.begin(), img->bwd.end());
   std::reverse(img->bwd_bytes.begin(), img->bwd_bytes.end());
+  std::reverse(img->bwd_set.begin(), img->bwd_set.end());
   img->part_doubles = part;
 
   // outputs: [E, N, dgamma[p], dbeta[p]]

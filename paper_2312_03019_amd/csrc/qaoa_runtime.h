@@ -84,6 +84,7 @@ struct RunImage {
   int nout = 0;
   std::vector<double> pass_bytes;    // algorithmic HBM bytes per forward pass
   std::vector<double> bwd_bytes;     // ... and per backward pass
+  std::vector<int> fwd_set, bwd_set; // qubit set (0 = low set) of each forward / backward pass
   bool complemented = false;         // final state stored at z ^ (2^n - 1)
 };
 

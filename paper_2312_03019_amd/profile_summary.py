@@ -5,9 +5,9 @@
       forward-pass kernels (every k_fwd shape) aggregated per precision.
   python -m paper_2312_03019_amd.profile_summary counters --fetch F.csv --write W.csv \\
       --copy-bytes B --cmd "..." > out.md
-      HBM bytes per forward-pass launch from FETCH_SIZE / WRITE_SIZE (KiB per
-      dispatch), each scaled by what the same counter reports for the plain copy
-      kernel k_copy moving a known B bytes each way.
+      HBM bytes per dispatch of each pass kernel (k_fwd / k_bwd shape) from
+      FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by what the same
+      counter reports for the plain copy kernel k_copy moving B bytes each way.
   python -m paper_2312_03019_amd.profile_summary table --csv C.csv --cmd "..." > out.md
       per-dispatch averages of every counter in one --pmc run, per kernel.
 
@@ -42,10 +42,12 @@ def stats(a):
     rows = list(csv.DictReader(open(path)))
     out = ["# Kernel durations (rocprofv3 --kernel-trace --stats)", "", "Command:", "", "```", a.cmd, "```", "",
            "| kernel | calls | avg ms | min ms | max ms | share |", "|---|---|---|---|---|---|"]
-    agg = {}
+    agg, avg = {}, []
     for r in rows:
         name, calls = r["Name"], int(r["Calls"])
         tot = float(r["TotalDurationNs"])
+        if "k_fwd" in name or "k_bwd" in name or "k_copy" in name:
+            avg.append(f"- avg_ms {short_name(name)}: {float(r['AverageNs']) / 1e6:.4f}")
         out.append(f"| `{name[:110]}` | {calls} | {float(r['AverageNs']) / 1e6:.3f} | "
                    f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
         p = _prec(name)
@@ -57,6 +59,7 @@ def stats(a):
         label = "complex64" if p == "float" else "complex128"
         out.append(f"- k_fwd_{label}_launches: {c}")
         out.append(f"- k_fwd_{label}_mean_launch_ms: {t / c / 1e6:.4f}")
+    out += avg
     out.append(f"- kernel_source_sha256: {kernel_sha()}")
     print("\n".join(out))
 
@@ -71,7 +74,16 @@ def _per_dispatch(path, counter):
     return vals
 
 
+def short_name(name):
+    """Kernel name without namespace and parameter list, e.g. k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>."""
+    m = re.search(r"(k_\w+<[^>]*>)", name) or re.search(r"qaoa::(k_\w+)", name)
+    return m.group(1) if m else name[:60]
+
+
 def counters(a):
+    """HBM bytes per dispatch of every pass kernel (k_fwd, k_bwd), FETCH_SIZE and
+    WRITE_SIZE each scaled by what the counter reports for k_copy moving a known
+    number of bytes each way."""
     fetch = _per_dispatch(a.fetch, "FETCH_SIZE")
     write = _per_dispatch(a.write, "WRITE_SIZE")
 
@@ -79,29 +91,32 @@ def counters(a):
         return [v for (n, v) in d.values() if pred(n)]
 
     is_copy = lambda n: "k_copy" in n
-    is_fwd = lambda n: "k_fwd<float" in n
     cf, cw = pick(fetch, is_copy), pick(write, is_copy)
-    ff, fw = pick(fetch, is_fwd), pick(write, is_fwd)
-    if not (cf and cw and ff and fw):
-        sys.exit("missing k_copy or k_fwd dispatches in the counter files")
+    kernels = sorted({short_name(n) for (n, _) in list(fetch.values()) + list(write.values())
+                      if "k_fwd" in n or "k_bwd" in n})
+    if not (cf and cw and kernels):
+        sys.exit("missing k_copy or pass-kernel dispatches in the counter files")
     kib = lambda xs: sum(xs) / len(xs)
     sf = a.copy_bytes / (kib(cf) * 1024.0)       # bytes per reported KiB, reads
     sw = a.copy_bytes / (kib(cw) * 1024.0)       # bytes per reported KiB, writes
-    f_b, w_b = kib(ff) * 1024.0 * sf, kib(fw) * 1024.0 * sw
-    out = ["# HBM traffic of the forward pass (rocprofv3 --pmc)", "", "Commands (one counter per run):", "", "```",
+    out = ["# HBM traffic per pass kernel (rocprofv3 --pmc)", "", "Commands (one counter per run):", "", "```",
            a.cmd, "```", "",
-           f"Copy kernel k_copy, {a.copy_bytes} bytes read and written per dispatch: FETCH_SIZE "
+           f"Copy kernel k_copy, {a.copy_bytes:.0f} bytes read and written per dispatch: FETCH_SIZE "
            f"{kib(cf):.1f} KiB, WRITE_SIZE {kib(cw):.1f} KiB per dispatch, so one reported KiB is "
            f"{sf:.3f} KiB read and {sw:.3f} KiB written.", "",
-           f"Forward pass k_fwd (complex64, all shapes, {len(ff)} dispatches): FETCH_SIZE {kib(ff):.1f} KiB, "
-           f"WRITE_SIZE {kib(fw):.1f} KiB per dispatch (raw), scaled {f_b / 1e9:.3f} GB read + "
-           f"{w_b / 1e9:.3f} GB written.", ""]
-    if a.alg_bytes:
-        out.append(f"Algorithmic bytes per launch (mean over the run's passes): {a.alg_bytes / 1e9:.3f} GB; "
-                   f"measured / algorithmic = {(f_b + w_b) / a.alg_bytes:.3f}.")
-        out.append("")
-    out += [f"- fetch_scale: {sf:.4f}", f"- write_scale: {sw:.4f}",
-            f"- traffic_bytes_per_launch: {f_b + w_b:.6e}",
+           "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB | written GB | traffic GB |",
+           "|---|---|---|---|---|---|---|"]
+    fields = []
+    for k in kernels:
+        ff = pick(fetch, lambda n, k=k: short_name(n) == k)
+        fw = pick(write, lambda n, k=k: short_name(n) == k)
+        if not (ff and fw):
+            continue
+        f_b, w_b = kib(ff) * 1024.0 * sf, kib(fw) * 1024.0 * sw
+        out.append(f"| `{k}` | {len(ff)} | {kib(ff):.1f} | {kib(fw):.1f} | {f_b / 1e9:.3f} | {w_b / 1e9:.3f} | "
+                   f"{(f_b + w_b) / 1e9:.3f} |")
+        fields.append(f"- traffic {k}: {f_b + w_b:.6e}")
+    out += ["", f"- fetch_scale: {sf:.4f}", f"- write_scale: {sw:.4f}", *fields,
             f"- kernel_source_sha256: {kernel_sha()}"]
     print("\n".join(out))
 
@@ -110,7 +125,7 @@ def table(a):
     sums, calls = {}, {}
     for r in csv.DictReader(open(a.csv)):
         name = r["Kernel_Name"]
-        if "k_fwd" not in name and "k_copy" not in name:
+        if "k_fwd" not in name and "k_bwd" not in name and "k_copy" not in name:
             continue
         d = sums.setdefault(name, {})
         d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
@@ -137,7 +152,6 @@ def main():
     c.add_argument("--fetch", required=True)
     c.add_argument("--write", required=True)
     c.add_argument("--copy-bytes", type=float, required=True)
-    c.add_argument("--alg-bytes", type=float, default=0.0)
     c.add_argument("--cmd", required=True)
     t = sub.add_parser("table")
     t.add_argument("--csv", required=True)

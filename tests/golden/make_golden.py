@@ -9,7 +9,11 @@ inputs of workloads/:
   grad_gnp_n24     G(24, 0.3) unweighted, p = 8, 64 parameter sets: <C> and
                    the adjoint gradient (16 values) of every set
 
-Usage: python tests/golden/make_golden.py [--skip-n30] [--only-max-cut]   (n = 30 needs ~24 GiB RAM)
+  grad_gnp_n24_fd  FP64 central differences (h = 1e-6) of <C> for the first
+                   four of those parameter sets (32 oracle runs per set)
+
+Usage: python tests/golden/make_golden.py [--skip-n30] [--only-max-cut] [--only-fd]
+(n = 30 needs ~24 GiB RAM)
 """
 from __future__ import annotations
 
@@ -31,6 +35,17 @@ OUT = os.path.join(HERE, "oracle_fullsize.json")
 def main():
     skip30 = "--skip-n30" in sys.argv
     out = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    if "--only-fd" in sys.argv:
+        prob, params = W.grad_gnp_n24()
+        sets = []
+        t0 = time.time()
+        for i, (g, b) in enumerate(params[:4]):
+            dg, db = oracle.grad_fd(prob.n, prob.edges, prob.weights, g, b, h=1e-6)
+            sets.append({"set": i, "dgamma": dg.tolist(), "dbeta": db.tolist()})
+            print(f"grad_gnp_n24 FD set {i} ({time.time() - t0:.1f} s)", flush=True)
+        out["grad_gnp_n24_fd"] = {"h": 1e-6, "sets": sets}
+        json.dump(out, open(OUT, "w"), indent=1)
+        return
     if "--only-max-cut" in sys.argv:
         prob, _, _ = W.weighted_3reg_n30()
         ct = oracle.cut_table(prob.n, prob.edges, prob.weights)

@@ -35,15 +35,18 @@ def test_bench_refuses_more_than_one_gpu():
 def test_counter_traffic_is_used_only_for_the_current_kernel(tmp_path):
     bench = _load("bench_under_test", os.path.join(ROOT, "bench.py"))
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    k = "k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>"
     good = tmp_path / "good.md"
-    good.write_text(f"text\n- traffic_bytes_per_launch: 1.5e+10\n- kernel_source_sha256: {sha}\n")
-    t, src = bench.pmc_traffic(str(good))
+    good.write_text(f"text\n- traffic {k}: 1.5e+10\n- kernel_source_sha256: {sha}\n")
+    t, src = bench.pmc_traffic(str(good), k)
     assert t == 1.5e10 and src.endswith("good.md")
+    t, src = bench.pmc_traffic(str(good), "k_fwd<float, 5, 13, 3, 1, 0, 0, 0, 1>")
+    assert t is None and "no counters" in src
     stale = tmp_path / "stale.md"
-    stale.write_text("- traffic_bytes_per_launch: 1.5e+10\n- kernel_source_sha256: " + "0" * 64 + "\n")
-    t, src = bench.pmc_traffic(str(stale))
+    stale.write_text(f"- traffic {k}: 1.5e+10\n- kernel_source_sha256: " + "0" * 64 + "\n")
+    t, src = bench.pmc_traffic(str(stale), k)
     assert t is None and "changed" in src
-    t, src = bench.pmc_traffic(str(tmp_path / "missing.md"))
+    t, src = bench.pmc_traffic(str(tmp_path / "missing.md"), k)
     assert t is None
 
 
@@ -56,19 +59,27 @@ def _pmc_csv(path, counter, rows):
 
 def test_counter_summary_scales_by_the_copy_kernel(tmp_path, capsys):
     ps = _load("profile_summary_under_test", os.path.join(ROOT, "paper_2312_03019_amd", "profile_summary.py"))
-    copy = "qaoa::k_copy(HIP_vector_type<float, 4u> const*, HIP_vector_type<float, 4u>*, long)"
+    copy = "void qaoa::k_copy<4>(HIP_vector_type<float, 4u> const*, HIP_vector_type<float, 4u>*, long)"
     fwd = "void qaoa::k_fwd<float, 5, 13, 3, 1, 0, 0, 0, 1>(qaoa::PassDesc const*, int)"
+    mrg = "void qaoa::k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>(qaoa::PassDesc const*, int)"
     # the copy moves 1 MiB each way; FETCH_SIZE reports half the bytes read (split over two
     # rows of one dispatch), WRITE_SIZE all of the bytes written
-    _pmc_csv(tmp_path / "f.csv", "FETCH_SIZE", [(1, copy, 300.0), (1, copy, 212.0), (2, fwd, 1000.0), (3, fwd, 1200.0)])
-    _pmc_csv(tmp_path / "w.csv", "WRITE_SIZE", [(1, copy, 1024.0), (2, fwd, 1500.0), (3, fwd, 1700.0)])
+    _pmc_csv(tmp_path / "f.csv", "FETCH_SIZE", [(1, copy, 300.0), (1, copy, 212.0), (2, fwd, 1000.0), (3, fwd, 1200.0),
+                                                (4, mrg, 900.0)])
+    _pmc_csv(tmp_path / "w.csv", "WRITE_SIZE", [(1, copy, 1024.0), (2, fwd, 1500.0), (3, fwd, 1700.0), (4, mrg, 2000.0)])
     a = argparse.Namespace(fetch=str(tmp_path / "f.csv"), write=str(tmp_path / "w.csv"), copy_bytes=float(1 << 20),
-                           alg_bytes=0.0, cmd="synthetic")
+                           cmd="synthetic")
     ps.counters(a)
     out = capsys.readouterr().out
-    fields = dict(re.findall(r"^- (\w+): (\S+)$", out, re.M))
+    fields = dict(re.findall(r"^- ([\w ,<>-]+): (\S+)$", out, re.M))
     assert float(fields["fetch_scale"]) == pytest.approx(2.0)
     assert float(fields["write_scale"]) == pytest.approx(1.0)
-    # mean over the two k_fwd dispatches: 1100 KiB fetched (x2), 1600 KiB written (x1)
-    assert float(fields["traffic_bytes_per_launch"]) == pytest.approx((1100.0 * 2 + 1600.0) * 1024, rel=1e-6)
+    # per kernel: mean over its dispatches, FETCH_SIZE x2 + WRITE_SIZE x1
+    assert float(fields["traffic k_fwd<float, 5, 13, 3, 1, 0, 0, 0, 1>"]) == pytest.approx((1100.0 * 2 + 1600.0) * 1024)
+    assert float(fields["traffic k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>"]) == pytest.approx((900.0 * 2 + 2000.0) * 1024)
     assert fields["kernel_source_sha256"] == hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    # bench reads the dominant kernel's figure from such a summary
+    bench = _load("bench_under_test2", os.path.join(ROOT, "bench.py"))
+    (tmp_path / "c.md").write_text(out)
+    t, src = bench.pmc_traffic(str(tmp_path / "c.md"), "k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>")
+    assert t == pytest.approx((900.0 * 2 + 2000.0) * 1024, rel=1e-6)

@@ -382,3 +382,18 @@ def test_sampling_frequencies_match_probabilities():
     obs = counts[keep].astype(float)
     exp *= obs.sum() / exp.sum()
     assert chisquare(obs, exp).pvalue > 1e-4
+
+
+def test_stored_oracle_adjoint_matches_stored_central_differences():
+    # tests/golden/make_golden.py --only-fd: FP64 central differences (h = 1e-6) of the
+    # oracle's <C> for the first four n=24 parameter sets; the stored adjoint gradients of
+    # the same sets must agree within the FD error (truncation ~h^2, rounding ~eps |E| / h)
+    import json
+    d = json.load(open(os.path.join(GOLD, "oracle_fullsize.json")))
+    E = d["grad_gnp_n24"]["num_edges"]
+    fd = d["grad_gnp_n24_fd"]["sets"]
+    assert len(fd) == 4
+    for x in fd:
+        r = d["grad_gnp_n24"]["sets"][x["set"]]
+        assert np.max(np.abs(np.array(x["dgamma"]) - r["dgamma"])) < 1e-8 * E
+        assert np.max(np.abs(np.array(x["dbeta"]) - r["dbeta"])) < 1e-8 * E
