@@ -482,7 +482,9 @@ def main():
 
     torch.cuda.set_device(0)
     if a.only_grad_hbm:
-        print(json.dumps({"grad_hbm": grad_hbm_bench(q, torch, W)}), flush=True)
+        cg = copy_ceiling(q, torch, block_bytes=16384)      # also the counters' reference copy
+        torch.cuda.empty_cache()
+        print(json.dumps({"grad_hbm": grad_hbm_bench(q, torch, W), "copy_ceiling_gbps_16k_per_wg": cg}), flush=True)
         return
     prob, g, b = W.weighted_3reg_n30(n=a.n, p=a.p)
     stream = torch.cuda.current_stream()

@@ -86,6 +86,24 @@ __device__ __forceinline__ void stg(QGLOBAL cx<R>* p, cx<R> a) {
   *reinterpret_cast<QGLOBAL typename Prec<R>::V*>(p) = v;
 }
 
+// The pass kernels stream the state: every amplitude is read once and written
+// once per pass, with no reuse through the caches.  Non-temporal loads and
+// stores (streaming cache policy) together measured about 9% faster than the
+// default policy for a contiguous in-place sweep of 8 GiB, and a few percent
+// for the strided high-set tiles; either one alone gained nothing.
+template <typename R>
+__device__ __forceinline__ cx<R> ldg_nt(const QGLOBAL cx<R>* p) {
+  const typename Prec<R>::V v = __builtin_nontemporal_load(reinterpret_cast<const QGLOBAL typename Prec<R>::V*>(p));
+  return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void stg_nt(QGLOBAL cx<R>* p, cx<R> a) {
+  typename Prec<R>::V v;
+  v.x = a.re;
+  v.y = a.im;
+  __builtin_nontemporal_store(v, reinterpret_cast<QGLOBAL typename Prec<R>::V*>(p));
+}
+
 template <typename R>
 __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
@@ -142,20 +160,44 @@ struct RegOffsets {
   }
 };
 
-template <typename R, int LOGR>
+template <typename R, int LOGR, bool NT>
 __device__ __forceinline__ void load_tile(cx<R> (&v)[1 << LOGR], const QGLOBAL cx<R>* __restrict__ src,
                                           uint64_t zt, const RegOffsets<LOGR>& ro) {
   const QGLOBAL cx<R>* base = src + zt;
 #pragma unroll
-  for (int j = 0; j < (1 << LOGR); ++j) v[j] = ldg(base + ro(j));
+  for (int j = 0; j < (1 << LOGR); ++j) v[j] = NT ? ldg_nt(base + ro(j)) : ldg(base + ro(j));
 }
 
-template <typename R, int LOGR>
+template <typename R, int LOGR, bool NT>
 __device__ __forceinline__ void store_tile(const cx<R> (&v)[1 << LOGR], QGLOBAL cx<R>* __restrict__ dst,
                                            uint64_t zt, const RegOffsets<LOGR>& ro) {
   QGLOBAL cx<R>* base = dst + zt;
 #pragma unroll
-  for (int j = 0; j < (1 << LOGR); ++j) stg(base + ro(j), v[j]);
+  for (int j = 0; j < (1 << LOGR); ++j) {
+    if (NT) stg_nt(base + ro(j), v[j]);
+    else stg(base + ro(j), v[j]);
+  }
+}
+
+// Cache policy and occupancy per pass shape, as measured on the n = 30 plans
+// (complex64 and complex128, 8 / 16 GiB): the streaming (non-temporal)
+// policy pays for the passes over high-set tiles and for every complex128
+// pass, not for the complex64 low-set passes, whose contiguous tiles stream
+// better with the default policy and four workgroups per CU.  The two-round
+// merged complex64 pass runs four workgroups per CU as well (127 VGPRs).
+template <typename R, int NRC, int NSC, int GEN, int EXP>
+__device__ constexpr bool fwd_streaming() {
+  return sizeof(R) == 8 || GEN == 1 || EXP > 0 || NSC == 2;
+}
+template <typename R, int NRC, int NSC, int GEN, int EXP, int HALF>
+constexpr int fwd_waves() {
+  return !HALF ? 2 : (sizeof(R) == 4 && ((NSC == 1 && GEN == 0 && EXP == 0 && NRC == 3) || (NSC == 2 && NRC == 2))) ? 4 : 3;
+}
+template <typename R, int NRC, int NSC, int NOSTORE>
+__device__ constexpr bool bwd_streaming() {
+  // not for the low-set passes (three rounds complex64, four complex128) nor the complex64 merged pass
+  return NRC > 0 && !(sizeof(R) == 4 && NRC == 3 && NSC == 1) && !(sizeof(R) == 8 && NRC == 4) &&
+         !(sizeof(R) == 4 && NSC == 2);
 }
 
 // Move the register contents from round mapping `from` to round mapping `to` through LDS.
@@ -500,9 +542,12 @@ __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
 //   accumulate <C> and the norm, 2 = also store lam = C psi.
 // With everything fixed the pass is straight-line code (no register merges).
 template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int EXP, int HALF>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(HALF ? 3 : 2, HALF ? 3 : 2)))
+__global__ void __launch_bounds__(kMaxThreads)
+    __attribute__((amdgpu_waves_per_eu(fwd_waves<R, NRC, NSC, GEN, EXP, HALF>(),
+                                       fwd_waves<R, NRC, NSC, GEN, EXP, HALF>())))
 k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
   constexpr int NR = 1 << LOGR;
+  constexpr bool NT = NRC > 0 ? fwd_streaming<R, NRC, NSC, GEN, EXP>() : sizeof(R) == 8;
   __shared__ cx<R> lds[1 << (KB - HALF)];
   __shared__ double red[2 * (kMaxThreads / 64)];
   const uint32_t tid = threadIdx.x;
@@ -527,7 +572,7 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) v[j] = {a, (R)0};
   } else {
-    load_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, ro0);
+    load_tile<R, LOGR, NT>(v, gmem<cx<R>>(D.psi), zt0, ro0);
   }
   // Site values: the per-thread cut decomposition; segment s uses site s & 1,
   // at the round it starts in, and <C> uses site 0.  Full-LDS kernels run two
@@ -624,7 +669,8 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
       aN += pr;
       if (exp == 2) {
         const cx<R> lv = {(R)(cj * v[J].re), (R)(cj * v[J].im)};
-        stg(lam + (zt0 | ro0(J)), lv);
+        if (NT) stg_nt(lam + (zt0 | ro0(J)), lv);
+        else stg(lam + (zt0 | ro0(J)), lv);
       }
     }
     block_reduce2(aE, aN, red, blockDim.x);
@@ -634,7 +680,7 @@ k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
       part[D.ntiles + g] = aN;
     }
   }
-  if (!(flags & PF_NO_STORE)) store_tile<R, LOGR>(v, gmem<cx<R>>(D.psi), zt0, ro0);
+  if (!(flags & PF_NO_STORE)) store_tile<R, LOGR, NT>(v, gmem<cx<R>>(D.psi), zt0, ro0);
 }
 
 // Im sum over register pairs of conj(l_a) f_b + conj(l_b) f_a, for the qubits
@@ -676,6 +722,7 @@ template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int NOSTORE>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
   constexpr int NR = 1 << LOGR;
+  constexpr bool NT = bwd_streaming<R, NRC, NSC, NOSTORE>();
   constexpr bool SHAPED = NRC > 0;
   __shared__ cx<R> lds[1 << KB];
   __shared__ double red[2 * (kMaxThreads / 64)];
@@ -698,8 +745,8 @@ k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
   const RegOffsets<LOGR> ro0(cmem<uint64_t>(D.rbit0));
   const uint64_t zt0 = tile_zbase(D, g) | tmem<KB>(tbase<LOGR>(tid, D.rb[0]), cmem<int8_t>(D.map.tpos));
   cx<R> f[NR], l[NR];
-  load_tile<R, LOGR>(f, phi, zt0, ro0);
-  load_tile<R, LOGR>(l, lamp, zt0, ro0);
+  load_tile<R, LOGR, NT>(f, phi, zt0, ro0);
+  load_tile<R, LOGR, NT>(l, lamp, zt0, ro0);
 
   auto has_phase = [&](int s) __attribute__((always_inline)) {
     return PHM >= 0 ? ((PHM >> s) & 1) != 0 : segs[s].has_phase != 0;
@@ -785,8 +832,8 @@ k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
     // instead of keeping all load addresses of both vectors live meanwhile.
     uint64_t zs = zt0;
     asm volatile("" : "+v"(zs));
-    store_tile<R, LOGR>(f, phi, zs, ro0);
-    store_tile<R, LOGR>(l, lamp, zs, ro0);
+    store_tile<R, LOGR, NT>(f, phi, zs, ro0);
+    store_tile<R, LOGR, NT>(l, lamp, zs, ro0);
   }
 }
 
