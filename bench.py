@@ -164,13 +164,18 @@ def serve_bench(q, W, nreq):
     res = [srv.wait(x) for x in tix]
     st = srv.stats()
     srv.close()
-    kinds = {}
+    kinds, small = {}, []
     for r, x in zip(trace, res):
         kinds.setdefault("grad" if r.want_grad else "expect", []).append(x["t_done"] - x["t_arrival"])
+        if not r.want_grad and r.problem.n <= 14:      # whole request in one workgroup
+            small.append(x["t_done"] - x["t_arrival"])
     out["poisson"] = {"rate_req_per_s": lam, "req_per_s": st["req_per_s"], "p50_s": st["p50_s"],
                       "p99_s": st["p99_s"], "failed": sum(1 for x in res if x["status"] != 0),
                       "p99_expect_s": float(np.percentile(kinds.get("expect", [0]), 99)),
-                      "p99_grad_s": float(np.percentile(kinds.get("grad", [0]), 99))}
+                      "p99_grad_s": float(np.percentile(kinds.get("grad", [0]), 99)),
+                      "one_workgroup_requests": len(small),
+                      "p50_one_workgroup_s": float(np.percentile(small, 50)) if small else None,
+                      "p99_one_workgroup_s": float(np.percentile(small, 99)) if small else None}
     out["requests"] = nreq
     out["workload"] = ("Poisson arrivals; family uniform {3-regular (even n), G(n,0.3), complete}; "
                        "n U{14..28}; weights U[0,1); p U{1..12}; 30% gradient; complex64; budget 200 GiB")

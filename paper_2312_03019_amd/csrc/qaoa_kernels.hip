@@ -838,6 +838,119 @@ k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
 }
 
 // ---------------------------------------------------------------------------
+// A whole small request in one workgroup (serving).  The state stays in LDS
+// for every layer: |+>^n, then per layer the cost phase exp(-i gamma C(z))
+// (C from Algorithm 3's popcounts when unweighted, else the FP64 sum over the
+// cut edges in canonical order; computed once per amplitude and kept in
+// registers as FP64) and exp(-i beta X) on every qubit, four (complex128:
+// three) qubits at a time in registers (the unitary 2x2 form), then <C> and the norm in FP64 with
+// a fixed reduction order.  Thread t owns amplitudes z = t + 1024 k for the
+// phase and the sums; for the mixer window [b, b + W) it holds the 2^W
+// amplitudes whose other bits are t's.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(kSmallThreads) k_small(const SmallDesc* __restrict__ descs) {
+  constexpr int MAXN = sizeof(R) == 4 ? kSmallMaxNC64 : kSmallMaxNC128;
+  constexpr int KPT = (1 << MAXN) / kSmallThreads;   // amplitudes per thread at the largest n
+  __shared__ cx<R> st[1 << MAXN];
+  __shared__ double red[2 * (kSmallThreads / 64)];
+  const SmallDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (n < 1 || n > MAXN) return;   // the host routes only sizes that fit (uniform: the whole workgroup)
+  const int N = 1 << n;
+  const uint32_t tid = threadIdx.x;
+  const QCONST GraphDev* g = cmem<GraphDev>(D.g);
+  const QCONST double* gam = cmem<double>(D.gamma);
+  const QCONST double* bet = cmem<double>(D.beta);
+  double cz[KPT];
+  const R amp0 = (R)exp2(-0.5 * n);
+#pragma unroll
+  for (int k = 0; k < KPT; ++k) {
+    const int z = (int)tid + k * kSmallThreads;
+    cz[k] = 0.0;
+    if (z < N) {
+      const uint64_t b = (uint64_t)z;
+      if (!g->weighted) {
+        int c = 0;
+        for (int v = 0; v < n; ++v) c += (int)__popcll(g->upper[v] & ((0ull - ((b >> v) & 1ull)) ^ b));
+        cz[k] = (double)c;
+      } else {
+        const QCONST int32_t* eu = cmem<int32_t>(g->eu);
+        const QCONST int32_t* ev = cmem<int32_t>(g->ev);
+        const QCONST double* ew = cmem<double>(g->ew);
+        double c = 0.0;
+        for (int e = 0; e < g->m; ++e)
+          if (((b >> eu[e]) ^ (b >> ev[e])) & 1ull) c += ew[e];
+        cz[k] = c;
+      }
+      st[z] = {amp0, (R)0};
+    }
+  }
+  __syncthreads();
+  constexpr int WMAX = sizeof(R) == 4 ? 4 : 3;   // register window (complex128: fewer registers)
+  const int W = n < WMAX ? n : WMAX;
+  const uint32_t active = 1u << (n - W);
+  for (int l = 0; l < D.p; ++l) {
+    const double gl = gam[l];
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int z = (int)tid + k * kSmallThreads;
+      if (z < N) st[z] = cmul(st[z], expmi<R>(gl * cz[k]));
+    }
+    __syncthreads();
+    const R c = (R)cos(bet[l]), s = (R)sin(bet[l]);
+    for (int b0 = 0; b0 < n; b0 += WMAX) {
+      const int b = b0 + W <= n ? b0 : n - W;    // window [b, b + W); bits below b0 are done
+      if (tid < active) {
+        const uint32_t base = ((tid >> b) << (b + W)) | (tid & ((1u << b) - 1u));
+        cx<R> v[1 << WMAX];
+#pragma unroll
+        for (int j = 0; j < (1 << WMAX); ++j)
+          if (j < (1 << W)) v[j] = st[base | ((uint32_t)j << b)];
+#pragma unroll
+        for (int k = 0; k < WMAX; ++k) {
+          if (k >= W || b + k < b0) continue;
+#pragma unroll
+          for (int j = 0; j < (1 << WMAX); ++j) {
+            if (j >= (1 << W) || (j & (1 << k))) continue;
+            const cx<R> a = v[j], e = v[j | (1 << k)];
+            v[j] = {c * a.re + s * e.im, c * a.im - s * e.re};             // c a - i s e
+            v[j | (1 << k)] = {c * e.re + s * a.im, c * e.im - s * a.re};  // -i s a + c e
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < (1 << WMAX); ++j)
+          if (j < (1 << W)) st[base | ((uint32_t)j << b)] = v[j];
+      }
+      __syncthreads();
+    }
+  }
+  double aE = 0.0, aN = 0.0;
+#pragma unroll
+  for (int k = 0; k < KPT; ++k) {
+    const int z = (int)tid + k * kSmallThreads;
+    if (z < N) {
+      const double pr = (double)st[z].re * st[z].re + (double)st[z].im * st[z].im;
+      aE = fma(pr, cz[k], aE);
+      aN += pr;
+    }
+  }
+  block_reduce2(aE, aN, red, kSmallThreads);
+  if (tid == 0) {
+    QGLOBAL double* o = gmem<double>(D.out);
+    o[0] = aE;
+    o[1] = aN;
+  }
+}
+
+hipError_t launch_small(int prec, const SmallDesc* d, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (prec == 1) hipLaunchKernelGGL(k_small<float>, dim3(count), dim3(kSmallThreads), 0, st, d);
+  else hipLaunchKernelGGL(k_small<double>, dim3(count), dim3(kSmallThreads), 0, st, d);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Deterministic second-stage sums: one workgroup per output, Neumaier
 // compensation per thread over a fixed stride, then a fixed-order combine.
 // ---------------------------------------------------------------------------

@@ -62,6 +62,8 @@ inline int fidelity_blocks(int64_t N) {
 // (fidelity_work(nblocks).bytes of device memory).
 hipError_t launch_fidelity_sums(int prec_a, const void* a, int prec_b, const void* b, int64_t N, int rev_b, char* work,
                                 int nblocks, hipStream_t st);
+// Whole small requests, one workgroup each (SmallDesc array in device memory).
+hipError_t launch_small(int prec, const SmallDesc* d, int count, hipStream_t st);
 // x[z] <-> x[N-1-z] in place (complements every index bit).
 hipError_t launch_reverse(int prec, void* x, int64_t N, hipStream_t st);
 // block_bytes: bytes per workgroup, 4096 or 16384.

@@ -142,6 +142,19 @@ struct PassDesc {
 // Per-tile cut table row: [C(zbase), dout_0 .. dout_{K-1}, 0...].
 constexpr int kTileCutStride = 16;
 
+// A whole small request evaluated by one workgroup (serving): the state
+// (2^n amplitudes, n <= kSmallMaxN for the precision) lives in LDS for all p
+// layers, so the request needs no HBM passes and completes within one launch.
+constexpr int kSmallMaxNC64 = 14;    // 2^14 complex64 = 128 KiB of LDS
+constexpr int kSmallMaxNC128 = 13;   // 2^13 complex128 = 128 KiB
+constexpr int kSmallThreads = 1024;
+struct SmallDesc {
+  const GraphDev *g;
+  const double *gamma, *beta;   // p values each
+  double *out;                  // <C>, norm
+  int32_t n, p;
+};
+
 // One output value: *out = scale * (sum of the listed spans, in order).
 struct ReduceJob {
   int32_t span_begin, span_end;  // into the span array

@@ -85,6 +85,7 @@ struct SReq {
   int p = 0;
   std::vector<double> gamma, beta;
   bool grad = false;
+  bool small = false;   // whole request in one workgroup (state in LDS), no HBM passes
   double t_arrival = 0, t_admit = -1, t_done = -1;
   int status = QAOA_EPENDING;
   double expect = 0, norm = 0;
@@ -156,7 +157,7 @@ struct qaoa_server {
 
 void qaoa_server::release_mem(SReq* r) {
   if (!r->has_mem) return;
-  arena.release(r->off_psi, r->sz_psi);
+  if (r->sz_psi) arena.release(r->off_psi, r->sz_psi);
   if (r->sz_lam) arena.release(r->off_lam, r->sz_lam);
   arena.release(r->off_aux, r->sz_aux);
   r->has_mem = false;
@@ -245,13 +246,13 @@ int qaoa_server::step_once(uint64_t step) {
     while (!queue.empty() && (int)active.size() < max_slots && !free_slots.empty()) {
       SReq* r = queue.front();
       size_t a = 0, b = 0, c = 0;
-      if (!arena.alloc(r->sz_psi, &a)) break;
+      if (r->sz_psi && !arena.alloc(r->sz_psi, &a)) break;
       if (r->sz_lam && !arena.alloc(r->sz_lam, &b)) {
-        arena.release(a, r->sz_psi);
+        if (r->sz_psi) arena.release(a, r->sz_psi);
         break;
       }
       if (!arena.alloc(r->sz_aux, &c)) {
-        arena.release(a, r->sz_psi);
+        if (r->sz_psi) arena.release(a, r->sz_psi);
         if (r->sz_lam) arena.release(b, r->sz_lam);
         break;
       }
@@ -273,7 +274,9 @@ int qaoa_server::step_once(uint64_t step) {
 
   // ---- host staging: new requests' graph + run images, then step descriptors
   size_t hneed = 0;
-  for (SReq* r : fresh) hneed += align256(r->graph_bytes) + align256(r->lay.total);
+  for (SReq* r : fresh)
+    hneed += align256(r->graph_bytes) + (r->small ? align256((2 * (size_t)r->p + 2) * sizeof(double))
+                                                    : align256(r->lay.total));
   struct Group {
     bool bwd;
     int logr, nthreads, shape;
@@ -298,14 +301,44 @@ int qaoa_server::step_once(uint64_t step) {
     g->tiles += d.ntiles;
     g->d.push_back(d);
   }
-  size_t dneed = 0;
+  size_t nsmall = 0;
+  for (SReq* r : fresh) nsmall += r->small ? 1 : 0;
+  size_t dneed = align256(nsmall * sizeof(SmallDesc));
   for (auto& g : groups) dneed += align256(g.d.size() * sizeof(PassDesc));
   if (grow_pinned(&hstage[par], &hstage_cap[par], hneed + dneed + 256) ||
       grow_dev(&dstage[par], &dstage_cap[par], dneed + 256))
     return QAOA_ENOMEM;
 
   size_t hoff = 0;
+  std::vector<SmallDesc> smalls;
+  std::vector<SReq*> small_reqs;
   for (SReq* r : fresh) {
+    if (r->small) {
+      // graph image, then gamma, beta and the two outputs
+      char* aux = arena.base + r->off_aux;
+      r->dev_aux = aux;
+      build_dev_graph_image(r->hg, hstage[par] + hoff, aux);
+      double* hg = (double*)(hstage[par] + hoff + align256(r->graph_bytes));
+      std::copy(r->gamma.begin(), r->gamma.end(), hg);
+      std::copy(r->beta.begin(), r->beta.end(), hg + r->p);
+      hg[2 * r->p] = hg[2 * r->p + 1] = 0.0;
+      double* dg = (double*)(aux + align256(r->graph_bytes));
+      const size_t bytes = align256(r->graph_bytes) + (2 * (size_t)r->p + 2) * sizeof(double);
+      if (hipMemcpyAsync(aux, hstage[par] + hoff, bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return QAOA_EDEVICE;
+      SmallDesc sd;
+      sd.g = (const GraphDev*)aux;
+      sd.gamma = dg;
+      sd.beta = dg + r->p;
+      sd.out = dg + 2 * r->p;
+      sd.n = r->hg.n;
+      sd.p = r->p;
+      smalls.push_back(sd);
+      small_reqs.push_back(r);
+      hoff += align256(r->graph_bytes) + align256((2 * (size_t)r->p + 2) * sizeof(double));
+      r->uploaded = true;
+      continue;
+    }
     char* psi = arena.base + r->off_psi;
     char* lam = r->sz_lam ? arena.base + r->off_lam : nullptr;
     char* aux = arena.base + r->off_aux;
@@ -356,6 +389,11 @@ int qaoa_server::step_once(uint64_t step) {
     if (r->next == r->nlaunch) fin.push_back(r);
   }
   size_t doff = 0;
+  const size_t small_off = doff;
+  if (!smalls.empty()) {
+    memcpy(hstage[par] + hoff + doff, smalls.data(), smalls.size() * sizeof(SmallDesc));
+    doff += align256(smalls.size() * sizeof(SmallDesc));
+  }
   std::vector<size_t> goff;
   for (auto& g : groups) {
     memcpy(hstage[par] + hoff + doff, g.d.data(), g.d.size() * sizeof(PassDesc));
@@ -369,6 +407,18 @@ int qaoa_server::step_once(uint64_t step) {
     if (launch_pass(prec == QAOA_C64 ? 1 : 0, g.bwd, g.logr, g.shape, (const PassDesc*)(dstage[par] + goff[i]),
                     (int)g.d.size(), g.tiles, g.nthreads, stream) != hipSuccess)
       return QAOA_EDEVICE;
+  }
+  if (!smalls.empty()) {
+    if (launch_small(prec == QAOA_C64 ? 1 : 0, (const SmallDesc*)(dstage[par] + small_off), (int)smalls.size(),
+                     stream) != hipSuccess)
+      return QAOA_EDEVICE;
+    for (size_t i = 0; i < small_reqs.size(); ++i) {
+      SReq* r = small_reqs[i];
+      if (hipMemcpyAsync(host_out + (size_t)r->slot * out_stride, smalls[i].out, 2 * sizeof(double),
+                         hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return QAOA_EDEVICE;
+      r->reduce_issued = true;
+    }
   }
   for (SReq* r : fin) {
     char* dimg = r->dev_aux + align256(r->graph_bytes);
@@ -387,6 +437,7 @@ int qaoa_server::step_once(uint64_t step) {
     // Later users of this memory are ordered after these kernels on the one
     // stream, so finished requests give their memory back immediately.
     std::lock_guard<std::mutex> lk(mu);
+    fin.insert(fin.end(), small_reqs.begin(), small_reqs.end());
     for (SReq* r : fin) {
       release_mem(r);
       active.erase(std::find(active.begin(), active.end(), r));
@@ -501,22 +552,30 @@ int qaoa_serve_submit(qaoa_server* s, const qaoa_request* q, double arrival_time
   r->beta.assign(q->beta, q->beta + q->p);
   r->grad = q->want_grad != 0;
   const PrecCfg pc = prec_cfg(s->prec);
+  r->small = !r->grad && r->hg.n <= (s->prec == QAOA_C64 ? kSmallMaxNC64 : kSmallMaxNC128);
+  if (r->small) {
+    r->graph_bytes = dev_graph_bytes(r->hg);
+    r->sz_aux = align256(r->graph_bytes) + align256((2 * (size_t)r->p + 2) * sizeof(double));
+    r->nf = r->nlaunch = 0;
+  }
   RunRequest rq{&r->hg, s->prec, r->p, r->gamma.data(), r->beta.data(), r->grad, nullptr, nullptr, nullptr};
-  build_run(rq, &r->img);
-  r->lay = image_layout(r->img, s->prec);
-  r->graph_bytes = dev_graph_bytes(r->hg);
-  r->sz_psi = ((size_t)1 << r->hg.n) * pc.elem;
-  r->sz_lam = r->grad ? r->sz_psi : 0;
-  r->tcut_doubles = tile_cut_doubles(r->hg.n, s->prec);
-  r->sz_aux = align256(r->graph_bytes) + align256(r->lay.total) +
-              align256((r->img.part_doubles + r->img.nout) * sizeof(double)) +
-              align256(r->tcut_doubles * sizeof(double));
-  r->nf = (int)r->img.fwd.size();
-  r->nlaunch = r->nf + (int)r->img.bwd.size();
-  int K;
-  tile_shape(r->hg.n, pc, &K, &r->logr);
-  r->nthreads = 1 << (K - r->logr);
-  r->ntiles = (int64_t)1 << (r->hg.n - K);
+  if (!r->small) {
+    build_run(rq, &r->img);
+    r->lay = image_layout(r->img, s->prec);
+    r->graph_bytes = dev_graph_bytes(r->hg);
+    r->sz_psi = ((size_t)1 << r->hg.n) * pc.elem;
+    r->sz_lam = r->grad ? r->sz_psi : 0;
+    r->tcut_doubles = tile_cut_doubles(r->hg.n, s->prec);
+    r->sz_aux = align256(r->graph_bytes) + align256(r->lay.total) +
+                align256((r->img.part_doubles + r->img.nout) * sizeof(double)) +
+                align256(r->tcut_doubles * sizeof(double));
+    r->nf = (int)r->img.fwd.size();
+    r->nlaunch = r->nf + (int)r->img.bwd.size();
+    int K;
+    tile_shape(r->hg.n, pc, &K, &r->logr);
+    r->nthreads = 1 << (K - r->logr);
+    r->ntiles = (int64_t)1 << (r->hg.n - K);
+  }
   if (r->footprint() > s->budget) {
     set_error("request needs %zu bytes, budget is %zu", r->footprint(), s->budget);
     delete r;

@@ -84,3 +84,49 @@ def test_cancel():
     assert res[-1]["status"] == q.QAOA_ECANCELED and res[-2]["status"] == q.QAOA_ECANCELED
     for r, x in zip(tr[:4], res[:4]):
         _check(r, x, "c64")
+
+
+# Expectation requests small enough for one workgroup's LDS (complex64 n <= 14,
+# complex128 n <= 13) run whole inside one workgroup (state in LDS for every
+# layer) within the step that admits them; larger and gradient requests take
+# the pass path.  Both paths must match the oracle, and every request must give
+# bitwise the same result alone and in a mix of both kinds.
+@pytest.mark.parametrize("prec,nmax", [("c64", 14), ("c128", 13)])
+def test_small_requests_in_one_workgroup(prec, nmax):
+    rng = W.SplitMix64(77)
+    reqs = []
+    for i, (n, kind, weighted) in enumerate([(1, "complete", False), (2, "gnp", True), (3, "complete", True),
+                                             (5, "gnp", False), (8, "3reg", True), (nmax - 1, "gnp", True),
+                                             (nmax, "complete", True), (nmax - nmax % 2, "3reg", False), (nmax, "gnp", False)]):
+        pr = W.random_problem(n, W.SplitMix64(700 + i), kind, weighted, 0.4)
+        p = 1 + (i % 5)
+        g, b = W.uniform_angles(p, rng)
+        reqs.append((pr, g, b, False))
+    # larger and gradient requests in the same mix
+    for i, (n, grad) in enumerate([(nmax + 2, False), (nmax, True), (18, False)]):
+        pr = W.random_problem(n, W.SplitMix64(800 + i), "gnp", True, 0.3)
+        g, b = W.uniform_angles(3, rng)
+        reqs.append((pr, g, b, grad))
+    srv = q.Server(4 << 30, max_slots=16, prec=prec)
+    tix = [srv.submit(pr.n, pr.edges, pr.weights, g, b, grad) for pr, g, b, grad in reqs]
+    res = [srv.wait(t, 60.0) for t in tix]
+    srv.close()
+    for (pr, g, b, grad), x in zip(reqs, res):
+        assert x["status"] == q.QAOA_OK, x
+        E = max(1, pr.num_edges)
+        if grad:
+            e, dg, db = oracle.grad(pr.n, pr.edges, pr.weights, g, b)
+            tol = 1e-3 * E if prec == "c64" else 1e-9 * E
+            assert np.max(np.abs(x["dgamma"] - dg)) <= tol and np.max(np.abs(x["dbeta"] - db)) <= tol
+        else:
+            e, nrm = oracle.run_expect(pr.n, pr.edges, pr.weights, g, b)
+            assert abs(x["norm"] - 1.0) <= (1e-5 if prec == "c64" else 1e-12)
+        err = abs(x["expect"] - e)
+        print(f"n={pr.n} grad={grad} {prec}: |d<C>|={err:.2e}")
+        assert err <= (1e-4 if prec == "c64" else 1e-10) * E
+    for (pr, g, b, grad), x in zip(reqs, res):
+        s1 = q.Server(4 << 30, max_slots=1, prec=prec)
+        y = s1.wait(s1.submit(pr.n, pr.edges, pr.weights, g, b, grad), 60.0)
+        s1.close()
+        assert y["expect"] == x["expect"] and y["norm"] == x["norm"]
+        assert np.array_equal(y["dgamma"], x["dgamma"]) and np.array_equal(y["dbeta"], x["dbeta"])
