@@ -286,6 +286,18 @@ def test_fidelity_definition():
     ref = abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
     assert f == pytest.approx(ref, rel=1e-13)
     assert oracle.fidelity(6, a, np.exp(0.3j) * 2 * a) == pytest.approx(1.0, abs=1e-14)
+    # orthogonal states: disjoint supports, and a state against its Gram-Schmidt complement
+    e0 = np.zeros(64, complex)
+    e0[:32] = a[:32]
+    e1 = np.zeros(64, complex)
+    e1[32:] = b[32:]
+    assert oracle.fidelity(6, e0, e1) == 0.0
+    c = b - np.vdot(a, b) / np.vdot(a, a) * a
+    assert oracle.fidelity(6, a, c) < 1e-28
+    # a known angle: |<x|y>|^2 = cos^2(t) for unit x, y = cos(t) x + sin(t) x_perp
+    x = a / np.linalg.norm(a)
+    xp = c / np.linalg.norm(c)
+    assert oracle.fidelity(6, x, np.cos(0.4) * x + np.sin(0.4) * xp) == pytest.approx(np.cos(0.4) ** 2, abs=1e-14)
 
 
 # --------------------------------------------------------------------------
