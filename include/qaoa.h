@@ -189,12 +189,34 @@ int qaoa_bind_state(qaoa_ctx *ctx, void *dev_ptr, size_t bytes);
 int qaoa_set_profiling(qaoa_ctx *ctx, int enable);
 
 /* Kernel times (ms) of the passes of the last run, in launch order (the
- * forward passes, then after qaoa_grad the backward passes), plus each pass's
+ * forward passes, then after qaoa_grad the backward passes; a chunked pass's
+ * time spans its chunk launches on its stream), plus each pass's
  * algorithmic HBM bytes (state bytes read + written, both vectors for a
  * backward pass).  Fills at most max entries of ms[] and bytes[] (either may
  * be NULL) and returns the pass count through *count.  Synchronises the
  * stream.  Only runs made while profiling is enabled are timed. */
 int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count);
+
+/* Chunked pass pairs (tuning).  With three qubit sets, every layer is one
+ * pass over the low set followed by one over a high set X; the pair is closed
+ * under chunks that fix the top qubits of the third set.  Runs whose state
+ * has at least min_state_bytes then execute each pair chunk by chunk (chunks
+ * of at least chunk_bytes), the high-set pass of chunk k on a second stream
+ * beside the low-set pass of chunk k + 1, so it reads its chunk while it is
+ * still cached.  The result is bitwise the same as unchunked.  chunk_bytes =
+ * 0 turns chunking off.  Defaults: complex64, 128 MiB chunks for states from
+ * 512 MiB (n >= 26); complex128, off. */
+int qaoa_set_chunking(qaoa_ctx *ctx, size_t chunk_bytes, size_t min_state_bytes);
+
+/* Inspection of the chunked pass pairs, no GPU needed (tests).  Chunk bits
+ * F of an n-qubit depth-p plan for the given chunk size (0 = not chunked)
+ * and, per pair, the memory bits its chunks fix (pair_fixed: up to max_pairs
+ * entries; the pair count through *npairs). */
+int qaoa_chunk_plan(int n, int prec, int p, size_t chunk_bytes, int *chunk_bits, uint64_t *pair_fixed,
+                    int max_pairs, int *npairs);
+/* The tile indices g of qubit set `set` that chunk k's launch covers, in
+ * launch order: 2^(n - K - chunk_bits) entries into g_out (K = tile bits). */
+int qaoa_chunk_tiles(int n, int prec, int set, uint64_t fixed_mem, int chunk_bits, int64_t k, int64_t *g_out);
 
 /* Measurement hook: pass `index` of the last run (forward passes in launch
  * order, then after qaoa_grad the backward passes), the qubit set it mixes
@@ -202,6 +224,12 @@ int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count
  * reports it without the parameter list (NUL-terminated, truncated to len).
  * QAOA_EINVAL for an index outside the last run. */
 int qaoa_pass_kernel(qaoa_ctx *ctx, int index, int *set_out, char *name, size_t len);
+
+/* Measurement hook: ms from the start of pass `first` to the end of pass
+ * `last` of the last timed run (for chunked pass pairs, whose two passes
+ * overlap on two streams, the pair's span is first = its low-set pass, last =
+ * its high-set pass).  Synchronises the stream. */
+int qaoa_pass_span(qaoa_ctx *ctx, int first, int last, float *ms);
 
 /* Plan of a run of depth p: number of HBM passes, number of qubit sets the
  * mixer is split into, and the qubits per set (sizes[] up to max_sets). */

@@ -81,6 +81,11 @@ _SIGS = {
     "qaoa_bind_state": (_I, [_P, _P, _SZ]),
     "qaoa_set_profiling": (_I, [_P, _I]),
     "qaoa_pass_times": (_I, [_P, ctypes.POINTER(ctypes.c_float), _DP, _I, ctypes.POINTER(_I)]),
+    "qaoa_set_chunking": (_I, [_P, _SZ, _SZ]),
+    "qaoa_pass_span": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_float)]),
+    "qaoa_chunk_plan": (_I, [_I, _I, _I, _SZ, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_uint64), _I,
+                             ctypes.POINTER(_I)]),
+    "qaoa_chunk_tiles": (_I, [_I, _I, _I, ctypes.c_uint64, _I, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "qaoa_pass_kernel": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.c_char_p, _SZ]),
     "qaoa_plan_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I), _I]),
     "qaoa_tile_map": (_I, [_I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(ctypes.c_int8),
@@ -256,6 +261,37 @@ def qaoa_pass_times(ctx, max_passes: int = 4096):
     _err(_lib.qaoa_pass_times(ctx, ms, by, max_passes, ctypes.byref(cnt)))
     k = min(cnt.value, max_passes)
     return np.array(ms[:k], dtype=np.float64), np.array(by[:k], dtype=np.float64)
+
+
+def qaoa_set_chunking(ctx, chunk_bytes: int, min_state_bytes: int = 1 << 30) -> None:
+    """Chunked pass pairs: chunks of at least chunk_bytes for states from min_state_bytes (0 = off)."""
+    _err(_lib.qaoa_set_chunking(ctx, int(chunk_bytes), int(min_state_bytes)))
+
+
+def qaoa_pass_span(ctx, first: int, last: int) -> float:
+    """ms from the start of pass `first` to the end of pass `last` of the last timed run."""
+    ms = ctypes.c_float()
+    _err(_lib.qaoa_pass_span(ctx, int(first), int(last), ctypes.byref(ms)))
+    return ms.value
+
+
+def qaoa_chunk_plan(n: int, prec: str, p: int, chunk_bytes: int):
+    """(chunk bits F, [fixed memory-bit mask of each pass pair]) of a plan; no GPU needed."""
+    F, cnt = ctypes.c_int(), ctypes.c_int()
+    fixed = (ctypes.c_uint64 * max(p, 1))()
+    _err(_lib.qaoa_chunk_plan(int(n), _PREC[prec], int(p), int(chunk_bytes), ctypes.byref(F), fixed, max(p, 1),
+                              ctypes.byref(cnt)))
+    return F.value, [int(fixed[i]) for i in range(cnt.value)]
+
+
+def qaoa_chunk_tiles(n: int, prec: str, set_index: int, fixed_mem: int, chunk_bits: int, k: int) -> np.ndarray:
+    """Tile indices of qubit set `set_index` covered by chunk k's launch; no GPU needed."""
+    K = 13 if _PREC[prec] == QAOA_C64 else 12
+    count = (1 << max(0, n - min(n, K))) >> chunk_bits
+    out = np.zeros(max(count, 1), dtype=np.int64)
+    _err(_lib.qaoa_chunk_tiles(int(n), _PREC[prec], int(set_index), ctypes.c_uint64(fixed_mem), int(chunk_bits),
+                               int(k), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out[:count]
 
 
 def qaoa_pass_kernel(ctx, index: int):

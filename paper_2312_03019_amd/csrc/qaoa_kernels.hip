@@ -519,11 +519,15 @@ __device__ __forceinline__ int find_desc(const PassDesc* __restrict__ descs, int
 
 // Tile handled by this workgroup.  Workgroups are dealt round-robin to the
 // eight XCDs; for a single-descriptor launch, give each XCD a contiguous run
-// of tiles so its L2 and the HBM pages it opens see neighbouring addresses.
-__device__ __forceinline__ int64_t tile_of_block(const PassDesc& D, int ndesc) {
+// of the launch's tiles so its L2 and the HBM pages it opens see neighbouring
+// addresses, then map the launch-local index to the pass's tile index (the
+// identity unless the launch covers one chunk of the state).  The map is a
+// kernel argument, so this is scalar arithmetic on registers.
+__device__ __forceinline__ int64_t tile_of_block(const PassDesc& D, int ndesc, const LaunchMap& lm) {
   const int64_t wg = blockIdx.x;
-  if (ndesc == 1 && (gridDim.x & 7u) == 0) return (wg & 7) * (int64_t)(gridDim.x >> 3) + (wg >> 3);
-  return wg - D.tile_begin;
+  if (ndesc > 1) return wg - D.tile_begin;
+  const uint64_t t = (gridDim.x & 7u) == 0 ? (wg & 7) * (int64_t)(gridDim.x >> 3) + (wg >> 3) : wg;
+  return (int64_t)launch_tile(lm, t);
 }
 
 // Memory offset of tile g's index-0 amplitude (scalar arithmetic on the
@@ -545,14 +549,14 @@ template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int 
 __global__ void __launch_bounds__(kMaxThreads)
     __attribute__((amdgpu_waves_per_eu(fwd_waves<R, NRC, NSC, GEN, EXP, HALF>(),
                                        fwd_waves<R, NRC, NSC, GEN, EXP, HALF>())))
-k_fwd(const PassDesc* __restrict__ descs, int ndesc) {
+k_fwd(const PassDesc* __restrict__ descs, int ndesc, LaunchMap lm) {
   constexpr int NR = 1 << LOGR;
   constexpr bool NT = NRC > 0 ? fwd_streaming<R, NRC, NSC, GEN, EXP>() : sizeof(R) == 8;
   __shared__ cx<R> lds[1 << (KB - HALF)];
   __shared__ double red[2 * (kMaxThreads / 64)];
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
-  const int64_t g = tile_of_block(D, ndesc);
+  const int64_t g = tile_of_block(D, ndesc, lm);
   const int nth = blockDim.x;
   const int nr = NRC > 0 ? NRC : D.nrounds;
   const int nseg = NSC > 0 ? NSC : D.nseg;
@@ -720,7 +724,7 @@ __device__ __forceinline__ double dbeta_round(const cx<R> (&f)[1 << LOGR], const
 // LDS (two workgroups per CU either way, with 2 x 2^LOGR amplitudes per thread).
 template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int NOSTORE>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
+k_bwd(const PassDesc* __restrict__ descs, int ndesc, LaunchMap lm) {
   constexpr int NR = 1 << LOGR;
   constexpr bool NT = bwd_streaming<R, NRC, NSC, NOSTORE>();
   constexpr bool SHAPED = NRC > 0;
@@ -728,7 +732,7 @@ k_bwd(const PassDesc* __restrict__ descs, int ndesc) {
   __shared__ double red[2 * (kMaxThreads / 64)];
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
-  const int64_t g = tile_of_block(D, ndesc);
+  const int64_t g = tile_of_block(D, ndesc, lm);
   const int nth = blockDim.x;
   const int nr = NRC > 0 ? NRC : D.nrounds;
   const int nseg = NSC > 0 ? NSC : D.nseg;
@@ -1085,12 +1089,13 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s_, flo
 // Launchers
 // ---------------------------------------------------------------------------
 template <typename R, int KB, int LOGR>
-static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, dim3 grid, dim3 block, hipStream_t st) {
+static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, const LaunchMap& lm, dim3 grid, dim3 block,
+                              hipStream_t st) {
   constexpr int HALF = 1;   // full-width tiles move through half the LDS
   switch (shape) {
 #define QAOA_FWD(NRC, CODE, NSC, PHM, GEN, EXP)                                                              \
   case NRC * 8 + CODE:                                                                                      \
-    hipLaunchKernelGGL((k_fwd<R, LOGR, KB, NRC, NSC, PHM, GEN, EXP, HALF>), grid, block, 0, st, d, ndesc);  \
+    hipLaunchKernelGGL((k_fwd<R, LOGR, KB, NRC, NSC, PHM, GEN, EXP, HALF>), grid, block, 0, st, d, ndesc, lm); \
     return;
 #define QAOA_FWD_NR(NRC)                                      \
   QAOA_FWD(NRC, kShapeFirst, 1, 1, 1, 0)                      \
@@ -1110,12 +1115,13 @@ static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, dim3 grid
 #undef QAOA_FWD_NR
 #undef QAOA_FWD
     default:
-      hipLaunchKernelGGL((k_fwd<R, LOGR, KB, 0, 0, -1, -1, -1, 0>), grid, block, 0, st, d, ndesc);
+      hipLaunchKernelGGL((k_fwd<R, LOGR, KB, 0, 0, -1, -1, -1, 0>), grid, block, 0, st, d, ndesc, lm);
   }
 }
 
 template <typename R, int KB>
-static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDesc* d, int ndesc, int64_t nblocks,
+static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDesc* d, int ndesc, const LaunchMap& lm,
+                                int64_t nblocks,
                                 int nthreads, hipStream_t st) {
   const dim3 grid((unsigned)nblocks), block((unsigned)nthreads);
   constexpr int LMAX = sizeof(R) == 4 ? kLogRC64 : kLogRC128;
@@ -1125,7 +1131,7 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
       switch (shape) {
 #define QAOA_BWD(NRC, CODE, NSC, PHM, NOSTORE)                                                            \
   case NRC * 8 + CODE:                                                                                    \
-    hipLaunchKernelGGL((k_bwd<R, LMAX, KB, NRC, NSC, PHM, NOSTORE>), grid, block, 0, st, d, ndesc);       \
+    hipLaunchKernelGGL((k_bwd<R, LMAX, KB, NRC, NSC, PHM, NOSTORE>), grid, block, 0, st, d, ndesc, lm);   \
     return hipGetLastError();
 #define QAOA_BWD_NR(NRC)                              \
   QAOA_BWD(NRC, kShapeFirst, 1, 1, 1)                 \
@@ -1142,7 +1148,7 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
       }
     }
 #define QAOA_BWD(LR) \
-  if (logr == LR) hipLaunchKernelGGL((k_bwd<R, LR, KB, 0, 0, -1, -1>), grid, block, 0, st, d, ndesc);
+  if (logr == LR) hipLaunchKernelGGL((k_bwd<R, LR, KB, 0, 0, -1, -1>), grid, block, 0, st, d, ndesc, lm);
     QAOA_BWD(1)
     QAOA_BWD(2)
     QAOA_BWD(3)
@@ -1152,11 +1158,11 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
     return hipGetLastError();
   }
   if (logr == LMAX) {
-    launch_fwd_shaped<R, KB, LMAX>(shape, d, ndesc, grid, block, st);
+    launch_fwd_shaped<R, KB, LMAX>(shape, d, ndesc, lm, grid, block, st);
     return hipGetLastError();
   }
 #define QAOA_GEN(LR) \
-  if (logr == LR) hipLaunchKernelGGL((k_fwd<R, LR, KB, 0, 0, -1, -1, -1, 0>), grid, block, 0, st, d, ndesc);
+  if (logr == LR) hipLaunchKernelGGL((k_fwd<R, LR, KB, 0, 0, -1, -1, -1, 0>), grid, block, 0, st, d, ndesc, lm);
   QAOA_GEN(1)
   QAOA_GEN(2)
   QAOA_GEN(3)
@@ -1166,10 +1172,10 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
 }
 
 hipError_t launch_pass(int prec, bool backward, int logr, int shape, const PassDesc* d, int ndesc, int64_t nblocks,
-                       int nthreads, hipStream_t st) {
+                       int nthreads, hipStream_t st, const LaunchMap& lm) {
   if (prec == 1)
-    return launch_pass_t<float, kTileBitsC64>(backward, logr, shape, d, ndesc, nblocks, nthreads, st);
-  return launch_pass_t<double, kTileBitsC128>(backward, logr, shape, d, ndesc, nblocks, nthreads, st);
+    return launch_pass_t<float, kTileBitsC64>(backward, logr, shape, d, ndesc, lm, nblocks, nthreads, st);
+  return launch_pass_t<double, kTileBitsC128>(backward, logr, shape, d, ndesc, lm, nblocks, nthreads, st);
 }
 
 // Mirrors the specialisations launch_pass_t selects (same cases, same

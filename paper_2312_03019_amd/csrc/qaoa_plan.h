@@ -139,6 +139,33 @@ struct PassDesc {
   uint64_t rbit0[kMaxLogR];  // memory bit (as a mask) of each register bit of round 0
 };
 
+// Which tiles one launch covers: workgroup-local tile index t -> the pass's
+// tile index g = gfix | OR over r of (t & mask[r]) << shift[r].  The identity
+// (one run, gfix 0) covers every tile; a chunked launch deposits t into the
+// index bits left free by the chunk and ORs the chunk's fixed bits in.
+constexpr int kLaunchRuns = 10;
+struct LaunchMap {
+  uint64_t gfix;
+  uint64_t mask[kLaunchRuns];
+  int8_t shift[kLaunchRuns];
+  int32_t nruns;
+};
+// The pass tile index of launch-local tile t (used by the pass kernels and
+// by the host-side inspection of chunk plans).
+__host__ __device__ inline uint64_t launch_tile(const LaunchMap& m, uint64_t t) {
+  uint64_t g = m.gfix;
+#pragma unroll
+  for (int r = 0; r < kLaunchRuns; ++r)
+    if (r < m.nruns) g |= (t & m.mask[r]) << m.shift[r];
+  return g;
+}
+inline LaunchMap identity_launch() {
+  LaunchMap m{};
+  m.mask[0] = ~0ull;
+  m.nruns = 1;
+  return m;
+}
+
 // Per-tile cut table row: [C(zbase), dout_0 .. dout_{K-1}, 0...].
 constexpr int kTileCutStride = 16;
 

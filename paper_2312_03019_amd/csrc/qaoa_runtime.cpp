@@ -369,6 +369,34 @@ static int backward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const 
   return code ? d.nrounds * 8 + code : 0;
 }
 
+// Chunked pass pairs: with three sets the schedule is a high set (the first
+// pass), then per layer the low set and a high set X (sets 1 and 2 alternate).
+// Each pair (low, X) is closed under chunks that fix qubits of the third set
+// Y, so the pair can run chunk by chunk, the second pass finding its chunk in
+// cache.  The top F qubits of Y are fixed, F from the chunk size (a launch map
+// holds F + 1 runs).  Returns F (0 = no chunking) and the fixed memory bits of
+// every pair.
+int chunk_plan(const std::vector<SetGeom>& sets, const std::vector<PassSpec>& sched, int p, double state_bytes,
+               size_t chunk_bytes, std::vector<uint64_t>* fixed_out) {
+  fixed_out->clear();
+  if (chunk_bytes == 0 || sets.size() != 3 || p < 1 || sched.size() != (size_t)(2 * p + 1)) return 0;
+  int F = 0;
+  while (F < kLaunchRuns - 1 && state_bytes / (double)((int64_t)1 << (F + 1)) >= (double)chunk_bytes) ++F;
+  for (int i = 1; i <= p && F > 0; ++i) {
+    const int x = sched[2 * i].set, y = 3 - x;
+    if (sched[2 * i - 1].set != 0 || x < 1 || x > 2) return fixed_out->clear(), 0;
+    F = std::min(F, sets[y].k);
+  }
+  if (F == 0) return 0;
+  for (int i = 1; i <= p; ++i) {
+    const SetGeom& Y = sets[3 - sched[2 * i].set];
+    uint64_t fixed = 0;
+    for (int t = Y.K - 1, c = 0; c < F; --t, ++c) fixed |= 1ull << Y.map.tpos[t];   // Y's top qubits
+    fixed_out->push_back(fixed);
+  }
+  return F;
+}
+
 void build_run(const RunRequest& rq, RunImage* img) {
   const HostGraph& hg = *rq.hg;
   const int n = hg.n;
@@ -513,6 +541,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
     }
   }
   img->complemented = (mode1_layers & 1) != 0;
+  img->chunk_bits = chunk_plan(sets, sched, rq.p, state_bytes, rq.chunk_bytes, &img->pair_fixed);
   if (rq.grad) {
     // Scalars of the factored adjoint sweep (SegDesc): walk the passes and
     // segments in the order the sweep undoes them, with the rounds of each
@@ -600,6 +629,28 @@ ImageLayout image_layout(const RunImage& img, int prec) {
   L.off_bwd = off; off = align_up(off + img.bwd.size() * sizeof(PassDesc), 256);
   L.total = off;
   return L;
+}
+
+LaunchMap chunk_launch_map(const TileMap& map, int nfree, uint64_t fixed_mem, int64_t k) {
+  LaunchMap m{};
+  int j = 0, t = 0, r = -1;
+  for (int b = 0; b < 64 && j < 64; ++b) {   // fixed memory bits in ascending order -> bits of k
+    if (!((fixed_mem >> b) & 1ull)) continue;
+    for (int i = 0; i < nfree; ++i)
+      if (map.gpos[i] == b) m.gfix |= (uint64_t)((k >> j) & 1) << i;
+    ++j;
+  }
+  for (int i = 0; i < nfree; ++i) {           // free index bits: local bit t -> index bit i
+    if ((fixed_mem >> map.gpos[i]) & 1ull) continue;
+    if (r < 0 || (i - t) != m.shift[r]) {      // a skipped (fixed) bit starts a new run
+      ++r;
+      m.shift[r] = (int8_t)(i - t);
+    }
+    m.mask[r] |= 1ull << t;
+    ++t;
+  }
+  m.nruns = r + 1;
+  return m;
 }
 
 size_t tile_cut_doubles(int n, int prec) {

@@ -86,6 +86,11 @@ struct RunImage {
   std::vector<double> bwd_bytes;     // ... and per backward pass
   std::vector<int> fwd_set, bwd_set; // qubit set (0 = low set) of each forward / backward pass
   bool complemented = false;         // final state stored at z ^ (2^n - 1)
+  // Chunked pass pairs (three-set plans): forward passes 2i-1 (low set) and
+  // 2i (a high set X) run chunk by chunk, 2^chunk_bits chunks each, a chunk
+  // fixing pair_fixed[i-1] (memory bits of the third set Y) to its index.
+  int chunk_bits = 0;
+  std::vector<uint64_t> pair_fixed;
 };
 
 struct RunRequest {
@@ -98,6 +103,7 @@ struct RunRequest {
   void* psi;                // device
   void* lam;                // device (grad)
   const GraphDev* g;        // device
+  size_t chunk_bytes = 0;   // forward pass pairs in chunks of about this many state bytes (0 = off)
 };
 
 // Layout of the device region holding one run image.
@@ -115,6 +121,15 @@ ImageLayout image_layout(const RunImage& img, int prec);
 // `part` and the output array `out` (nout doubles, device).
 void pack_run(RunImage& img, const ImageLayout& lay, int prec, void* host_buf, char* dev_region,
               double* part, double* out, const double* tcut);
+// Chunk bits F of the pass pairs of a plan (0 = no chunking) and, per pair,
+// the memory bits the chunks fix (see build_run).
+int chunk_plan(const std::vector<SetGeom>& sets, const std::vector<PassSpec>& sched, int p, double state_bytes,
+               size_t chunk_bytes, std::vector<uint64_t>* fixed_out);
+// Launch map of chunk k of a pass whose tile index g spans nfree bits with
+// g bit i at memory bit map.gpos[i]: the chunk fixes the memory bits in
+// fixed_mem to the bits of k (in ascending order of the memory bits) and
+// enumerates the remaining index bits in ascending order.
+LaunchMap chunk_launch_map(const TileMap& map, int nfree, uint64_t fixed_mem, int64_t k);
 // Doubles of the per-tile cut tables of all qubit sets of an n-qubit plan.
 size_t tile_cut_doubles(int n, int prec);
 // Fill them (device memory `tcut`) for the graph at device address g.

@@ -54,6 +54,25 @@ def stats(a):
         if p:
             c, t = agg.get(p, (0, 0.0))
             agg[p] = (c + calls, t + tot)
+    # per launch size: a chunked pass pair launches the same kernels over
+    # chunks of the state, so averages are split by the launch's workgroup count
+    trace = os.path.join(a.dir, f"{a.prefix}_kernel_trace.csv")
+    if os.path.exists(trace):
+        by = {}
+        for r in csv.DictReader(open(trace)):
+            name = r["Kernel_Name"]
+            if "k_fwd" not in name and "k_bwd" not in name:
+                continue
+            wgs = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+            c, t = by.get((short_name(name), wgs), (0, 0.0))
+            by[(short_name(name), wgs)] = (c + 1, t + d)
+        out += ["", "Pass kernels by launch size (workgroups per launch; whole passes launch every tile,",
+                "chunked pass pairs one chunk of tiles per launch):", "",
+                "| kernel | workgroups | launches | avg ms |", "|---|---|---|---|"]
+        for (k, w), (c, t) in sorted(by.items()):
+            out.append(f"| `{k}` | {w} | {c} | {t / c:.4f} |")
+            avg.append(f"- avg_ms {k} x{w}: {t / c:.4f}")
     out += ["", "Forward-pass kernel k_fwd, all shapes together:", ""]
     for p, (c, t) in sorted(agg.items()):
         label = "complex64" if p == "float" else "complex128"

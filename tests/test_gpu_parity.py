@@ -237,3 +237,32 @@ def test_bound_state_three_set_plan(prec, n):
     assert err < (1e-12 if prec == "c128" else 1e-5)
     assert abs(e - oracle.run_expect(n, pr.edges, None, g, _BETA_ODD)[0]) <= _tol(pr, prec)
     sim.close()
+
+
+# Chunked pass pairs (each low-set pass and the high-set pass after it run chunk
+# by chunk, the second on its own stream) compute every tile exactly as the
+# unchunked passes do, so the state, <C> and the gradient must be bitwise
+# equal; small chunks force chunking at sizes the oracle checks element-wise.
+@pytest.mark.parametrize("prec,n", [("c64", 23), ("c64", 24), ("c128", 22), ("c128", 23)])
+def test_chunked_pass_pairs_bitwise_equal(prec, n):
+    pr = _prob(340 + n, n, "gnp", True, 0.25)
+    g = [0.45, 1.1, 0.8, 0.3]
+    b = [0.3, 1.2, 0.5, 1.0]
+    res = {}
+    for label, chunk in (("plain", 0), ("chunked", 1 << 20)):
+        sim = q.Simulator(n, pr.edges, pr.weights, prec)
+        q.qaoa_set_chunking(sim.handle, chunk, 0)
+        e, nrm = sim.expect(g, b)
+        psi = sim.state()
+        eg, dg, db = sim.grad(g, b)
+        res[label] = (e, nrm, psi, eg, dg, db)
+        sim.close()
+    F, _ = q.qaoa_chunk_plan(n, prec, len(g), 1 << 20)
+    assert F >= 1
+    a, c = res["plain"], res["chunked"]
+    assert a[0] == c[0] and a[1] == c[1] and a[3] == c[3]
+    assert np.array_equal(a[2], c[2]) and np.array_equal(a[4], c[4]) and np.array_equal(a[5], c[5])
+    ref = oracle.evolve(n, pr.edges, pr.weights, g, b)
+    err = float(np.max(np.abs(c[2].astype(np.complex128) - ref)))
+    print(f"chunked n={n} {prec} F={F}: max|dpsi|={err:.3e}")
+    assert err < (1e-12 if prec == "c128" else 1e-5)
