@@ -204,9 +204,13 @@ int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count
  * of at least chunk_bytes), the high-set pass of chunk k on a second stream
  * beside the low-set pass of chunk k + 1, so it reads its chunk while it is
  * still cached.  The result is bitwise the same as unchunked.  chunk_bytes =
- * 0 turns chunking off.  Defaults: complex64, 128 MiB chunks for states from
+ * 0 turns chunking off.  streams (2, 3 or 4, else QAOA_EINVAL): 2 runs the
+ * high-set chunks on one extra stream, 3 alternates them over two, 4 also
+ * alternates the low-set chunks over two streams.  Defaults: complex64, 128
+ * MiB chunks for states from 512 MiB (n >= 26) on three streams; complex128,
+ * off.  Defaults: complex64, 128 MiB chunks for states from
  * 512 MiB (n >= 26); complex128, off. */
-int qaoa_set_chunking(qaoa_ctx *ctx, size_t chunk_bytes, size_t min_state_bytes);
+int qaoa_set_chunking(qaoa_ctx *ctx, size_t chunk_bytes, size_t min_state_bytes, int streams);
 
 /* Inspection of the chunked pass pairs, no GPU needed (tests).  Chunk bits
  * F of an n-qubit depth-p plan for the given chunk size (0 = not chunked)

@@ -81,7 +81,7 @@ _SIGS = {
     "qaoa_bind_state": (_I, [_P, _P, _SZ]),
     "qaoa_set_profiling": (_I, [_P, _I]),
     "qaoa_pass_times": (_I, [_P, ctypes.POINTER(ctypes.c_float), _DP, _I, ctypes.POINTER(_I)]),
-    "qaoa_set_chunking": (_I, [_P, _SZ, _SZ]),
+    "qaoa_set_chunking": (_I, [_P, _SZ, _SZ, _I]),
     "qaoa_pass_span": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_float)]),
     "qaoa_chunk_plan": (_I, [_I, _I, _I, _SZ, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_uint64), _I,
                              ctypes.POINTER(_I)]),
@@ -263,9 +263,10 @@ def qaoa_pass_times(ctx, max_passes: int = 4096):
     return np.array(ms[:k], dtype=np.float64), np.array(by[:k], dtype=np.float64)
 
 
-def qaoa_set_chunking(ctx, chunk_bytes: int, min_state_bytes: int = 1 << 30) -> None:
-    """Chunked pass pairs: chunks of at least chunk_bytes for states from min_state_bytes (0 = off)."""
-    _err(_lib.qaoa_set_chunking(ctx, int(chunk_bytes), int(min_state_bytes)))
+def qaoa_set_chunking(ctx, chunk_bytes: int, min_state_bytes: int = 512 << 20, streams: int = 2) -> None:
+    """Chunked pass pairs: chunks of at least chunk_bytes for states from min_state_bytes (0 = off),
+    spread over `streams` streams (2, 3 or 4)."""
+    _err(_lib.qaoa_set_chunking(ctx, int(chunk_bytes), int(min_state_bytes), int(streams)))
 
 
 def qaoa_pass_span(ctx, first: int, last: int) -> float:

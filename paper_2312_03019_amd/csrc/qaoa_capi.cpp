@@ -53,9 +53,10 @@ struct qaoa_ctx {
   // (defaults set by precision in qaoa_create)
   size_t chunk_bytes = 0;
   size_t chunk_min_state = 0;   // chunking only for states at least this large
-  hipStream_t stream2 = nullptr;
+  int chunk_streams = 2;               // 2: P2 chunks on one extra stream; 3: on two; 4: P1 on two as well
+  hipStream_t xs[3] = {nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> chunk_ev;
-  hipEvent_t join_ev = nullptr;
+  hipEvent_t join_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool upload_pending = false;
   bool have_state = false;
   bool have_expect = false;
@@ -192,18 +193,30 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
     }
   } else {
     // The first pass alone, then each (low set, high set) pair chunk by
-    // chunk: chunk k's first pass on the context stream, its second pass on
-    // stream2 once that chunk is written, while the context stream goes on
-    // with chunk k + 1.  The pair ends with stream2 joined back.  Pass times
-    // (profiling) span a pass's chunk launches on its stream.
+    // chunk: chunk k's first pass on a first-pass stream, its second pass on
+    // a second-pass stream once an event marks that chunk written, while the
+    // first-pass streams go on with the next chunks.  First-pass streams: the
+    // context stream (and xs[2] with four streams, alternating); second-pass
+    // streams: xs[0] (and xs[1] with three or four, alternating).  Every pair
+    // starts after the context stream's earlier work and ends with all
+    // streams joined back into it.  With profiling, the low-set pass's time
+    // spans its chunk launches on the context stream and the high-set pass's
+    // runs from its first chunk launch to the join, so the pair's span is
+    // qaoa_pass_span(low, high).
     const int64_t nch = (int64_t)1 << img.chunk_bits, per = ntiles >> img.chunk_bits;
-    if (!c->stream2) HIPCHK(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+    const int S = c->chunk_streams;
+    const int nx = S - 1;
+    for (int x = 0; x < nx; ++x)
+      if (!c->xs[x]) HIPCHK(hipStreamCreateWithFlags(&c->xs[x], hipStreamNonBlocking));
     while ((int64_t)c->chunk_ev.size() < nch) {
       hipEvent_t e;
       HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       c->chunk_ev.push_back(e);
     }
-    if (!c->join_ev) HIPCHK(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    for (int x = 0; x < 4; ++x)
+      if (!c->join_ev[x]) HIPCHK(hipEventCreateWithFlags(&c->join_ev[x], hipEventDisableTiming));
+    hipStream_t p1s[2] = {c->stream, S >= 4 ? c->xs[2] : c->stream};
+    hipStream_t p2s[2] = {c->xs[0], S >= 3 ? c->xs[1] : c->xs[0]};
     const int nfree = c->hg.n - K;
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[0], c->stream));
     HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[0].shape, dfwd, 1, ntiles, nthreads, c->stream));
@@ -212,21 +225,25 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
       const size_t a = 2 * pr + 1, b = a + 1;
       const uint64_t fixed = img.pair_fixed[pr];
       if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * a], c->stream));
+      // the extra streams start after the context stream's work so far
+      HIPCHK(hipEventRecord(c->join_ev[3], c->stream));
+      for (int x = 0; x < nx; ++x) HIPCHK(hipStreamWaitEvent(c->xs[x], c->join_ev[3], 0));
       for (int64_t k = 0; k < nch; ++k) {
+        hipStream_t s1 = p1s[k & 1], s2 = p2s[k & 1];
         const LaunchMap la = chunk_launch_map(img.fwd[a].map, nfree, fixed, k);
-        HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[a].shape, dfwd + a, 1, per, nthreads, c->stream, la));
-        HIPCHK(hipEventRecord(c->chunk_ev[k], c->stream));
-        HIPCHK(hipStreamWaitEvent(c->stream2, c->chunk_ev[k], 0));
-        if (c->profiling && k == 0) HIPCHK(hipEventRecord(c->ev[2 * b], c->stream2));
+        HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[a].shape, dfwd + a, 1, per, nthreads, s1, la));
+        HIPCHK(hipEventRecord(c->chunk_ev[k], s1));
+        HIPCHK(hipStreamWaitEvent(s2, c->chunk_ev[k], 0));
+        if (c->profiling && k == 0) HIPCHK(hipEventRecord(c->ev[2 * b], s2));
         const LaunchMap lb = chunk_launch_map(img.fwd[b].map, nfree, fixed, k);
-        HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[b].shape, dfwd + b, 1, per, nthreads, c->stream2, lb));
+        HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[b].shape, dfwd + b, 1, per, nthreads, s2, lb));
       }
-      if (c->profiling) {
-        HIPCHK(hipEventRecord(c->ev[2 * a + 1], c->stream));
-        HIPCHK(hipEventRecord(c->ev[2 * b + 1], c->stream2));
+      if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * a + 1], c->stream));
+      for (int x = 0; x < nx; ++x) {
+        HIPCHK(hipEventRecord(c->join_ev[x], c->xs[x]));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->join_ev[x], 0));
       }
-      HIPCHK(hipEventRecord(c->join_ev, c->stream2));
-      HIPCHK(hipStreamWaitEvent(c->stream, c->join_ev, 0));
+      if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * b + 1], c->stream));
     }
   }
   c->ntimed = c->profiling ? (int)(nf + nb) : 0;
@@ -361,10 +378,12 @@ int qaoa_create(int n, int num_edges, const int32_t* edges, const double* weight
   c->prec = prec;
   c->state_bytes = ((size_t)1 << n) * prec_cfg(prec).elem;
   if (prec == QAOA_C64) {
-    // measured on three-set plans (n = 26, 28, 30): 3-4% faster runs with
-    // 128 MiB chunks; complex128 runs measured slower chunked
+    // measured on three-set plans: n = 30 runs 8% faster with 128 MiB chunks
+    // and the high-set chunks alternating over two streams (3% at n = 26, 28);
+    // complex128 runs were slower chunked at every chunk size tried
     c->chunk_bytes = (size_t)128 << 20;
     c->chunk_min_state = (size_t)512 << 20;
+    c->chunk_streams = 3;
   }
   *out = c;
   return QAOA_OK;
@@ -381,8 +400,10 @@ void qaoa_destroy(qaoa_ctx* c) {
   if (c->dev_part) (void)hipFree(c->dev_part);
   if (c->dev_out) (void)hipFree(c->dev_out);
   for (hipEvent_t e : c->chunk_ev) (void)hipEventDestroy(e);
-  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
-  if (c->stream2) (void)hipStreamDestroy(c->stream2);
+  for (hipEvent_t e : c->join_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t x : c->xs)
+    if (x) (void)hipStreamDestroy(x);
   if (c->host_img) (void)hipHostFree(c->host_img);
   if (c->host_out) (void)hipHostFree(c->host_out);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
@@ -752,14 +773,19 @@ int qaoa_chunk_tiles(int n, int prec, int set, uint64_t fixed_mem, int chunk_bit
   return QAOA_OK;
 }
 
-int qaoa_set_chunking(qaoa_ctx* c, size_t chunk_bytes, size_t min_state_bytes) {
+int qaoa_set_chunking(qaoa_ctx* c, size_t chunk_bytes, size_t min_state_bytes, int streams) {
   Busy b(c);
   if (!b.ok) {
     set_error(c ? "context busy" : "context is NULL");
     return c ? QAOA_ESTATE : QAOA_EINVAL;
   }
+  if (streams < 2 || streams > 4) {
+    set_error("streams must be 2, 3 or 4");
+    return QAOA_EINVAL;
+  }
   c->chunk_bytes = chunk_bytes;
   c->chunk_min_state = min_state_bytes;
+  c->chunk_streams = streams;
   return QAOA_OK;
 }
 

@@ -249,9 +249,10 @@ def test_chunked_pass_pairs_bitwise_equal(prec, n):
     g = [0.45, 1.1, 0.8, 0.3]
     b = [0.3, 1.2, 0.5, 1.0]
     res = {}
-    for label, chunk in (("plain", 0), ("chunked", 1 << 20)):
+    for label, chunk, streams in (("plain", 0, 2), ("chunked", 1 << 20, 2), ("chunked3", 1 << 20, 3),
+                                  ("chunked4", 1 << 20, 4)):
         sim = q.Simulator(n, pr.edges, pr.weights, prec)
-        q.qaoa_set_chunking(sim.handle, chunk, 0)
+        q.qaoa_set_chunking(sim.handle, chunk, 0, streams)
         e, nrm = sim.expect(g, b)
         psi = sim.state()
         eg, dg, db = sim.grad(g, b)
@@ -259,9 +260,12 @@ def test_chunked_pass_pairs_bitwise_equal(prec, n):
         sim.close()
     F, _ = q.qaoa_chunk_plan(n, prec, len(g), 1 << 20)
     assert F >= 1
-    a, c = res["plain"], res["chunked"]
-    assert a[0] == c[0] and a[1] == c[1] and a[3] == c[3]
-    assert np.array_equal(a[2], c[2]) and np.array_equal(a[4], c[4]) and np.array_equal(a[5], c[5])
+    a = res["plain"]
+    for key in ("chunked", "chunked3", "chunked4"):
+        c = res[key]
+        assert a[0] == c[0] and a[1] == c[1] and a[3] == c[3], key
+        assert np.array_equal(a[2], c[2]) and np.array_equal(a[4], c[4]) and np.array_equal(a[5], c[5]), key
+    c = res["chunked"]
     ref = oracle.evolve(n, pr.edges, pr.weights, g, b)
     err = float(np.max(np.abs(c[2].astype(np.complex128) - ref)))
     print(f"chunked n={n} {prec} F={F}: max|dpsi|={err:.3e}")
