@@ -208,8 +208,7 @@ int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count
  * high-set chunks on one extra stream, 3 alternates them over two, 4 also
  * alternates the low-set chunks over two streams.  Defaults: complex64, 128
  * MiB chunks for states from 512 MiB (n >= 26) on three streams; complex128,
- * off.  Defaults: complex64, 128 MiB chunks for states from
- * 512 MiB (n >= 26); complex128, off. */
+ * off. */
 int qaoa_set_chunking(qaoa_ctx *ctx, size_t chunk_bytes, size_t min_state_bytes, int streams);
 
 /* Inspection of the chunked pass pairs, no GPU needed (tests).  Chunk bits
