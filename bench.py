@@ -574,7 +574,7 @@ def main():
                         "traffic_source": tsrc,
                         "kernel": dom,
                         "launches": "whole-pass launches (every tile of the pass in one launch); the headline run "
-                                    "pipelines each low-set/high-set pass pair over chunks on two streams (chunked_pairs)",
+                                    "pipelines each low-set/high-set pass pair over chunks on extra streams (chunked_pairs)",
                         "kernel_share_of_run": dk["share"],
                         "launches_timed": a.steps * dk["launches"],
                         "algorithmic_bytes_per_launch": dk["bytes_per_launch"],

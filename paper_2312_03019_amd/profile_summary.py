@@ -84,19 +84,27 @@ def stats(a):
 
 
 def _per_dispatch(path, counter):
+    """Dispatch id -> (kernel name with its launch size, summed counter value).  The launch
+    size (workgroups) tells whole-pass launches from the chunk launches of a pass pair."""
     vals = {}
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
         key = int(r["Dispatch_Id"])
-        vals[key] = (r["Kernel_Name"], vals.get(key, ("", 0.0))[1] + float(r["Counter_Value"]))
+        name = r["Kernel_Name"]
+        if "Grid_Size" in r and "Workgroup_Size" in r and ("k_fwd" in name or "k_bwd" in name):
+            name = f"{name} x{int(r['Grid_Size']) // max(1, int(r['Workgroup_Size']))}"
+        vals[key] = (name, vals.get(key, ("", 0.0))[1] + float(r["Counter_Value"]))
     return vals
 
 
 def short_name(name):
-    """Kernel name without namespace and parameter list, e.g. k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>."""
+    """Kernel name without namespace and parameter list, e.g. k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>,
+    keeping a launch-size suffix " x<workgroups>" when present."""
     m = re.search(r"(k_\w+<[^>]*>)", name) or re.search(r"qaoa::(k_\w+)", name)
-    return m.group(1) if m else name[:60]
+    base = m.group(1) if m else name[:60]
+    w = re.search(r" (x\d+)$", name)
+    return f"{base} {w.group(1)}" if w else base
 
 
 def counters(a):
@@ -135,6 +143,14 @@ def counters(a):
         out.append(f"| `{k}` | {len(ff)} | {kib(ff):.1f} | {kib(fw):.1f} | {f_b / 1e9:.3f} | {w_b / 1e9:.3f} | "
                    f"{(f_b + w_b) / 1e9:.3f} |")
         fields.append(f"- traffic {k}: {f_b + w_b:.6e}")
+    # the kernel's figure without a launch size is that of its largest launch (a whole pass)
+    by_base = {}
+    for fld in fields:
+        m = re.match(r"- traffic (.+) x(\d+): (\S+)$", fld)
+        if m and int(m.group(2)) > by_base.get(m.group(1), (0, ""))[0]:
+            by_base[m.group(1)] = (int(m.group(2)), m.group(3))
+    fields += [f"- traffic {k}: {v}" for k, (_, v) in sorted(by_base.items()) if f"- traffic {k}: " not in
+               "\n".join(fields)]
     out += ["", f"- fetch_scale: {sf:.4f}", f"- write_scale: {sw:.4f}", *fields,
             f"- kernel_source_sha256: {kernel_sha()}"]
     print("\n".join(out))
@@ -146,6 +162,8 @@ def table(a):
         name = r["Kernel_Name"]
         if "k_fwd" not in name and "k_bwd" not in name and "k_copy" not in name:
             continue
+        if "Grid_Size" in r and "Workgroup_Size" in r and "k_copy" not in name:
+            name = f"{short_name(name)} x{int(r['Grid_Size']) // max(1, int(r['Workgroup_Size']))}"
         d = sums.setdefault(name, {})
         d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
         calls.setdefault(name, set()).add(r["Dispatch_Id"])

@@ -78,6 +78,22 @@ def test_counter_summary_scales_by_the_copy_kernel(tmp_path, capsys):
     assert float(fields["traffic k_fwd<float, 5, 13, 3, 1, 0, 0, 0, 1>"]) == pytest.approx((1100.0 * 2 + 1600.0) * 1024)
     assert float(fields["traffic k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>"]) == pytest.approx((900.0 * 2 + 2000.0) * 1024)
     assert fields["kernel_source_sha256"] == hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    # with launch sizes in the CSV, whole-pass and chunk launches of one kernel are kept apart
+    with open(tmp_path / "f2.csv", "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Grid_Size,Workgroup_Size,Counter_Name,Counter_Value\n")
+        f.write(f'1,"{copy}",262144,256,FETCH_SIZE,512.0\n2,"{mrg}",33554432,256,FETCH_SIZE,900.0\n'
+                f'3,"{mrg}",524288,256,FETCH_SIZE,14.0\n')
+    with open(tmp_path / "w2.csv", "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Grid_Size,Workgroup_Size,Counter_Name,Counter_Value\n")
+        f.write(f'1,"{copy}",262144,256,WRITE_SIZE,1024.0\n2,"{mrg}",33554432,256,WRITE_SIZE,2000.0\n'
+                f'3,"{mrg}",524288,256,WRITE_SIZE,31.0\n')
+    ps.counters(argparse.Namespace(fetch=str(tmp_path / "f2.csv"), write=str(tmp_path / "w2.csv"),
+                                   copy_bytes=float(1 << 20), cmd="synthetic"))
+    out2 = capsys.readouterr().out
+    f2 = dict(re.findall(r"^- ([\w ,<>-]+): (\S+)$", out2, re.M))
+    assert float(f2["traffic k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1> x131072"]) == pytest.approx((900.0 * 2 + 2000.0) * 1024)
+    assert float(f2["traffic k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1> x2048"]) == pytest.approx((14.0 * 2 + 31.0) * 1024)
+    assert f2["traffic k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>"] == f2["traffic k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1> x131072"]
     # bench reads the dominant kernel's figure from such a summary
     bench = _load("bench_under_test2", os.path.join(ROOT, "bench.py"))
     (tmp_path / "c.md").write_text(out)
