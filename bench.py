@@ -256,6 +256,20 @@ def grad_bench(q, torch, W):
             out["c64"]["err_vs_device_c128_fd"] = _err_stats(
                 [np.concatenate([x[1], x[2]]) - f for x, (_, f) in zip(c64, diffs)], E)
         sim.close()
+        # the same 64 gradients submitted together to the serving loop, which runs
+        # them side by side (shared step launches) instead of one after another
+        for slots in (8, 64):
+            srv = q.Server(64 << 30, max_slots=slots, prec=prec)
+            srv.wait(srv.submit(prob.n, prob.edges, None, *params[0], want_grad=True))
+            t0 = time.perf_counter()
+            tix = [srv.submit(prob.n, prob.edges, None, g, b, want_grad=True) for g, b in params]
+            got = [srv.wait(t) for t in tix]
+            t = time.perf_counter() - t0
+            srv.close()
+            d_sv = [np.concatenate([np.asarray(x["dgamma"]) - np.array(r["dgamma"]),
+                                    np.asarray(x["dbeta"]) - np.array(r["dbeta"])]) for x, r in zip(got, ref)]
+            out[prec][f"served_{slots}_slots"] = {"grads_per_s": len(params) / t,
+                                                 "err_vs_oracle_adjoint": _err_stats(d_sv, E)}
     return out
 
 
