@@ -146,6 +146,58 @@ int check_angles(int p, const double* g, const double* b) {
   return QAOA_OK;
 }
 
+// One forward pass pair (passes a and a + 1) chunk by chunk: chunk k's first
+// pass on a first-pass stream, its second pass on a second-pass stream once an
+// event marks that chunk written, while the first-pass streams go on with the
+// next chunks.  First-pass streams: the
+// context stream (and xs[2] with four streams, alternating); second-pass
+// streams: xs[0] (and xs[1] with three or four, alternating).  The pair starts
+// after the context stream's earlier work and ends with all streams joined back
+// into it.  With profiling, the first pass's time spans its chunk launches on
+// the context stream and the second's runs from its first chunk launch to the
+// join, so the pair's span is qaoa_pass_span(a, a+1).
+static int launch_pair_chunks(qaoa_ctx* c, const RunImage& img, const PassDesc* dlist, size_t a, uint64_t fixed,
+                              int logr, int64_t ntiles, int nthreads) {
+  const std::vector<PassDesc>& list = img.fwd;
+  const size_t b = a + 1;
+  const int prec = prec_cfg(c->prec).prec;
+  const int64_t nch = (int64_t)1 << img.chunk_bits, per = ntiles >> img.chunk_bits;
+  const int S = c->chunk_streams;
+  const int nx = S - 1;
+  for (int x = 0; x < nx; ++x)
+    if (!c->xs[x]) HIPCHK(hipStreamCreateWithFlags(&c->xs[x], hipStreamNonBlocking));
+  while ((int64_t)c->chunk_ev.size() < nch) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->chunk_ev.push_back(e);
+  }
+  for (int x = 0; x < 4; ++x)
+    if (!c->join_ev[x]) HIPCHK(hipEventCreateWithFlags(&c->join_ev[x], hipEventDisableTiming));
+  hipStream_t p1s[2] = {c->stream, S >= 4 ? c->xs[2] : c->stream};
+  hipStream_t p2s[2] = {c->xs[0], S >= 3 ? c->xs[1] : c->xs[0]};
+  const int nfree = c->hg.n - list[a].K;
+  if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * a], c->stream));
+  HIPCHK(hipEventRecord(c->join_ev[3], c->stream));
+  for (int x = 0; x < nx; ++x) HIPCHK(hipStreamWaitEvent(c->xs[x], c->join_ev[3], 0));
+  for (int64_t k = 0; k < nch; ++k) {
+    hipStream_t s1 = p1s[k & 1], s2 = p2s[k & 1];
+    const LaunchMap la = chunk_launch_map(list[a].map, nfree, fixed, k);
+    HIPCHK(launch_pass(prec, false, logr, list[a].shape, dlist + a, 1, per, nthreads, s1, la));
+    HIPCHK(hipEventRecord(c->chunk_ev[k], s1));
+    HIPCHK(hipStreamWaitEvent(s2, c->chunk_ev[k], 0));
+    if (c->profiling && k == 0) HIPCHK(hipEventRecord(c->ev[2 * b], s2));
+    const LaunchMap lb = chunk_launch_map(list[b].map, nfree, fixed, k);
+    HIPCHK(launch_pass(prec, false, logr, list[b].shape, dlist + b, 1, per, nthreads, s2, lb));
+  }
+  if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * a + 1], c->stream));
+  for (int x = 0; x < nx; ++x) {
+    HIPCHK(hipEventRecord(c->join_ev[x], c->xs[x]));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->join_ev[x], 0));
+  }
+  if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * b + 1], c->stream));
+  return QAOA_OK;
+}
+
 // Build, upload and launch one run (forward, and the adjoint sweep if grad).
 int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool grad) {
   int rc = ensure_device(c);
@@ -192,59 +244,12 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
       if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * i + 1], c->stream));
     }
   } else {
-    // The first pass alone, then each (low set, high set) pair chunk by
-    // chunk: chunk k's first pass on a first-pass stream, its second pass on
-    // a second-pass stream once an event marks that chunk written, while the
-    // first-pass streams go on with the next chunks.  First-pass streams: the
-    // context stream (and xs[2] with four streams, alternating); second-pass
-    // streams: xs[0] (and xs[1] with three or four, alternating).  Every pair
-    // starts after the context stream's earlier work and ends with all
-    // streams joined back into it.  With profiling, the low-set pass's time
-    // spans its chunk launches on the context stream and the high-set pass's
-    // runs from its first chunk launch to the join, so the pair's span is
-    // qaoa_pass_span(low, high).
-    const int64_t nch = (int64_t)1 << img.chunk_bits, per = ntiles >> img.chunk_bits;
-    const int S = c->chunk_streams;
-    const int nx = S - 1;
-    for (int x = 0; x < nx; ++x)
-      if (!c->xs[x]) HIPCHK(hipStreamCreateWithFlags(&c->xs[x], hipStreamNonBlocking));
-    while ((int64_t)c->chunk_ev.size() < nch) {
-      hipEvent_t e;
-      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      c->chunk_ev.push_back(e);
-    }
-    for (int x = 0; x < 4; ++x)
-      if (!c->join_ev[x]) HIPCHK(hipEventCreateWithFlags(&c->join_ev[x], hipEventDisableTiming));
-    hipStream_t p1s[2] = {c->stream, S >= 4 ? c->xs[2] : c->stream};
-    hipStream_t p2s[2] = {c->xs[0], S >= 3 ? c->xs[1] : c->xs[0]};
-    const int nfree = c->hg.n - K;
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[0], c->stream));
     HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[0].shape, dfwd, 1, ntiles, nthreads, c->stream));
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[1], c->stream));
-    for (size_t pr = 0; pr < img.pair_fixed.size(); ++pr) {
-      const size_t a = 2 * pr + 1, b = a + 1;
-      const uint64_t fixed = img.pair_fixed[pr];
-      if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * a], c->stream));
-      // the extra streams start after the context stream's work so far
-      HIPCHK(hipEventRecord(c->join_ev[3], c->stream));
-      for (int x = 0; x < nx; ++x) HIPCHK(hipStreamWaitEvent(c->xs[x], c->join_ev[3], 0));
-      for (int64_t k = 0; k < nch; ++k) {
-        hipStream_t s1 = p1s[k & 1], s2 = p2s[k & 1];
-        const LaunchMap la = chunk_launch_map(img.fwd[a].map, nfree, fixed, k);
-        HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[a].shape, dfwd + a, 1, per, nthreads, s1, la));
-        HIPCHK(hipEventRecord(c->chunk_ev[k], s1));
-        HIPCHK(hipStreamWaitEvent(s2, c->chunk_ev[k], 0));
-        if (c->profiling && k == 0) HIPCHK(hipEventRecord(c->ev[2 * b], s2));
-        const LaunchMap lb = chunk_launch_map(img.fwd[b].map, nfree, fixed, k);
-        HIPCHK(launch_pass(pc.prec, false, logr, img.fwd[b].shape, dfwd + b, 1, per, nthreads, s2, lb));
-      }
-      if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * a + 1], c->stream));
-      for (int x = 0; x < nx; ++x) {
-        HIPCHK(hipEventRecord(c->join_ev[x], c->xs[x]));
-        HIPCHK(hipStreamWaitEvent(c->stream, c->join_ev[x], 0));
-      }
-      if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * b + 1], c->stream));
-    }
+    for (size_t pr = 0; pr < img.pair_fixed.size(); ++pr)
+      if ((rc = launch_pair_chunks(c, img, dfwd, 2 * pr + 1, img.pair_fixed[pr], logr, ntiles, nthreads)))
+        return rc;
   }
   c->ntimed = c->profiling ? (int)(nf + nb) : 0;
   c->pass_bytes = img.pass_bytes;
@@ -257,6 +262,8 @@ int launch_run(qaoa_ctx* c, int p, const double* gamma, const double* beta, bool
   c->pass_logr = logr;
   c->pass_nfwd = (int)nf;
   const PassDesc* dbwd = (const PassDesc*)(c->dev_img + lay.off_bwd);
+  // The adjoint sweep runs whole passes: paired and chunked like the forward
+  // passes (both vectors of a chunk per launch) it measured slower.
   for (size_t i = 0; i < nb; ++i) {
     if (c->profiling) HIPCHK(hipEventRecord(c->ev[2 * (nf + i)], c->stream));
     HIPCHK(launch_pass(pc.prec, true, logr, img.bwd[i].shape, dbwd + i, 1, ntiles, nthreads, c->stream));
