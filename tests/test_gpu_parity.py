@@ -270,3 +270,31 @@ def test_chunked_pass_pairs_bitwise_equal(prec, n):
     err = float(np.max(np.abs(c[2].astype(np.complex128) - ref)))
     print(f"chunked n={n} {prec} F={F}: max|dpsi|={err:.3e}")
     assert err < (1e-12 if prec == "c128" else 1e-5)
+
+
+# A chunked run on a caller's stream with a caller's buffer: the extra streams'
+# work is joined back into the caller's stream before qaoa_run returns, so work
+# the caller queues on its stream right after sees the finished state (here with
+# an odd number of shifted layers, so the library also reorders the buffer).
+@pytest.mark.parametrize("prec,n", [("c64", 24), ("c128", 23)])
+def test_chunked_pairs_join_the_caller_stream(prec, n):
+    pr = _prob(360 + n, n, "gnp", True, 0.3)
+    g = [0.45, 1.1, 0.8]
+    plain = q.Simulator(n, pr.edges, pr.weights, prec)
+    q.qaoa_set_chunking(plain.handle, 0, 0)
+    plain.expect(g, _BETA_ODD)
+    want = plain.state()
+    plain.close()
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    buf = torch.empty(1 << n, dtype=dt, device="cuda")
+    st = torch.cuda.Stream()
+    sim = q.Simulator(n, pr.edges, pr.weights, prec, stream=st)
+    q.qaoa_bind_state(sim.handle, buf)
+    q.qaoa_set_chunking(sim.handle, 1 << 20, 0, 3)
+    assert q.qaoa_chunk_plan(n, prec, len(g), 1 << 20)[0] >= 1
+    q.qaoa_run(sim.handle, g, _BETA_ODD)
+    with torch.cuda.stream(st):
+        snap = buf.clone()
+    st.synchronize()
+    assert np.array_equal(snap.cpu().numpy(), want)
+    sim.close()
