@@ -587,6 +587,7 @@ def main():
                         "traffic_unit": "GB per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-kernel scaled)",
                         "traffic_source": tsrc,
                         "kernel": dom,
+                        "workgroups_per_launch": 2 ** (a.n - len(q.qaoa_tile_map(a.n, "c64", 0)[0])),
                         "launches": "whole-pass launches (every tile of the pass in one launch); the headline run "
                                     "pipelines each low-set/high-set pass pair over chunks on extra streams (chunked_pairs)",
                         "kernel_share_of_run": dk["share"],
