@@ -123,6 +123,27 @@ def test_n30_p10_c64_against_c128():
     assert 1 - f <= 1e-5
 
 
+# The complex64 default at n=30 runs each (low set, high set) pass pair chunk
+# by chunk over three streams; whole passes must give bitwise the same state
+# and <C> (every tile computes the same arithmetic either way).
+def test_n30_p10_chunked_pairs_equal_whole_passes():
+    prob, g, b = W.weighted_3reg_n30()
+    dt = torch.complex64
+    bufs, es = [], []
+    for chunk in (128 << 20, 0):
+        buf = torch.empty(1 << prob.n, dtype=dt, device="cuda")
+        sim = q.Simulator(prob.n, prob.edges, prob.weights, "c64")
+        q.qaoa_bind_state(sim.handle, buf)
+        q.qaoa_set_chunking(sim.handle, chunk, 0, 3)
+        es.append(sim.expect(g, b))
+        sim.close()
+        bufs.append(buf)
+    assert q.qaoa_chunk_plan(prob.n, "c64", len(g), 128 << 20)[0] == 6
+    torch.cuda.synchronize()
+    assert es[0] == es[1]
+    assert torch.equal(bufs[0], bufs[1])
+
+
 def test_n26_config_both_precisions():
     ref = _golden("gnp_n26")
     prob, g, b = W.gnp_n26()
