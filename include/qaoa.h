@@ -218,7 +218,9 @@ int qaoa_set_chunking(qaoa_ctx *ctx, size_t chunk_bytes, size_t min_state_bytes,
 int qaoa_chunk_plan(int n, int prec, int p, size_t chunk_bytes, int *chunk_bits, uint64_t *pair_fixed,
                     int max_pairs, int *npairs);
 /* The tile indices g of qubit set `set` that chunk k's launch covers, in
- * launch order: 2^(n - K - chunk_bits) entries into g_out (K = tile bits). */
+ * launch order: 2^(n - K - chunk_bits) entries into g_out (K = tile bits).
+ * fixed_mem holds chunk_bits memory bits, all tile-index bits of the set, and
+ * 0 <= k < 2^chunk_bits; QAOA_EINVAL otherwise. */
 int qaoa_chunk_tiles(int n, int prec, int set, uint64_t fixed_mem, int chunk_bits, int64_t k, int64_t *g_out);
 
 /* Measurement hook: pass `index` of the last run (forward passes in launch

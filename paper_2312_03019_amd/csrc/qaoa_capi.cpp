@@ -774,6 +774,12 @@ int qaoa_chunk_tiles(int n, int prec, int set, uint64_t fixed_mem, int chunk_bit
     set_error("too few tile-index bits");
     return QAOA_EINVAL;
   }
+  uint64_t index_bits = 0;
+  for (int i = 0; i < nfree; ++i) index_bits |= 1ull << s[set].map.gpos[i];
+  if (fixed_mem & ~index_bits) {
+    set_error("fixed bits must be tile-index bits of the set");
+    return QAOA_EINVAL;
+  }
   const LaunchMap m = chunk_launch_map(s[set].map, nfree, fixed_mem, k);
   const int64_t per = ((int64_t)1 << nfree) >> chunk_bits;
   for (int64_t t = 0; t < per; ++t) g_out[t] = (int64_t)launch_tile(m, (uint64_t)t);

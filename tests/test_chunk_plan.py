@@ -79,3 +79,24 @@ def test_no_chunking_without_three_sets_or_when_off():
     assert q.qaoa_chunk_plan(30, "c64", 0, 1 << 20) == (0, [])      # no layers
     F, fixed = q.qaoa_chunk_plan(30, "c64", 10, 64 << 20)
     assert F == 7 and len(fixed) == 10                               # 8 GiB in 128 chunks of 64 MiB
+
+
+def test_inspection_calls_reject_bad_arguments():
+    with pytest.raises(q.QAOAError):
+        q.qaoa_chunk_plan(0, "c64", 4, 1 << 20)                      # n out of range
+    with pytest.raises(q.QAOAError):
+        q.qaoa_chunk_plan(40, "c64", 4, 1 << 20)
+    F, fixed = q.qaoa_chunk_plan(24, "c64", 3, 1 << 20)
+    assert F >= 1
+    with pytest.raises(q.QAOAError):
+        q.qaoa_chunk_tiles(24, "c64", 3, fixed[0], F, 0)             # no fourth set
+    with pytest.raises(q.QAOAError):
+        q.qaoa_chunk_tiles(24, "c64", 0, fixed[0], F, 1 << F)        # chunk index out of range
+    with pytest.raises(q.QAOAError):
+        q.qaoa_chunk_tiles(24, "c64", 0, fixed[0], F + 1, 0)         # bit count differs from the mask
+    with pytest.raises(q.QAOAError):
+        q.qaoa_chunk_tiles(24, "c64", 0, 1, 1, 0)                    # bit 0 is a tile bit, not an index bit
+    assert len(q.qaoa_chunk_tiles(24, "c64", 0, fixed[0], F, 0)) == (1 << (24 - 13)) >> F
+    # context calls on a NULL context
+    assert q._lib.qaoa_set_chunking(None, 1 << 20, 0, 3) == q.QAOA_EINVAL
+    assert q._lib.qaoa_pass_kernel(None, 0, None, None, 0) == q.QAOA_EINVAL
