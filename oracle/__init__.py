@@ -55,8 +55,9 @@ def load(path: Optional[str] = None):
     lib.oracle_grad.argtypes = [I, I, _ip, _dp, I, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_fidelity.argtypes = [I, _dp, _dp, _dp]
     lib.oracle_num_threads.argtypes = []
+    lib.oracle_amplitude_p1.argtypes = [I, I, _ip, _dp, D, D, ctypes.c_int64, _dp]
     for f in ("oracle_cut_table", "oracle_evolve", "oracle_expect", "oracle_run_expect",
-              "oracle_grad", "oracle_fidelity", "oracle_num_threads"):
+              "oracle_grad", "oracle_fidelity", "oracle_num_threads", "oracle_amplitude_p1"):
         getattr(lib, f).restype = I
     if path is None:
         _lib = lib
@@ -110,6 +111,18 @@ def evolve(n, edges, weights, gamma, beta, lib=None) -> np.ndarray:
     _check(lib.oracle_evolve(n, m, ep, wp, len(g), gp, bp, psi.ctypes.data_as(_dp)),
            "oracle_evolve")
     return psi.view(np.complex128)
+
+
+def amplitude_p1(n, edges, weights, gamma, beta, z, lib=None) -> complex:
+    """One amplitude psi_z of the depth-1 state, summed over the 2^n basis states
+    by its definition (no state vector): at n = 30 it needs seconds, not 8 GiB."""
+    lib = lib or load()
+    e, ep, m = _edges_ptr(edges)
+    w, wp = _w_ptr(weights)
+    out = np.empty(2, dtype=np.float64)
+    _check(lib.oracle_amplitude_p1(n, m, ep, wp, float(gamma), float(beta), int(z), out.ctypes.data_as(_dp)),
+           "oracle_amplitude_p1")
+    return complex(out[0], out[1])
 
 
 def expect_of_state(n, psi, cut) -> Tuple[float, float]:

@@ -11,8 +11,13 @@ inputs of workloads/:
 
   grad_gnp_n24_fd  FP64 central differences (h = 1e-6) of <C> for the first
                    four of those parameter sets (32 oracle runs per set)
+  weighted_3reg_n30_amp_p1  single amplitudes psi_z of the depth-1 state of the
+                   n = 30 graph (its first gamma and beta) at six indices z (distinct
+                   under the global flip), each summed over the 2^30 basis states
+                   (oracle.amplitude_p1); _shifted: the same at the second layer's
+                   angles (|sin beta| > |cos beta|), four indices
 
-Usage: python tests/golden/make_golden.py [--skip-n30] [--only-max-cut] [--only-fd]
+Usage: python tests/golden/make_golden.py [--skip-n30] [--only-max-cut] [--only-fd] [--only-amp]
 (n = 30 needs ~24 GiB RAM)
 """
 from __future__ import annotations
@@ -44,6 +49,29 @@ def main():
             sets.append({"set": i, "dgamma": dg.tolist(), "dbeta": db.tolist()})
             print(f"grad_gnp_n24 FD set {i} ({time.time() - t0:.1f} s)", flush=True)
         out["grad_gnp_n24_fd"] = {"h": 1e-6, "sets": sets}
+        json.dump(out, open(OUT, "w"), indent=1)
+        return
+    if "--only-amp" in sys.argv:
+        prob, g, b = W.weighted_3reg_n30()
+        n = prob.n
+        rng = W.SplitMix64(2024)
+        # psi(z) = psi(~z) for every depth (the global flip commutes with C and the
+        # mixer and fixes |+>^n), so the indices are taken from distinct flip orbits
+        zs = [0, int("01" * (n // 2), 2)] + [rng.next_u64() % (1 << n) for _ in range(4)]
+        amps = []
+        t0 = time.time()
+        for z in zs:
+            a = oracle.amplitude_p1(n, prob.edges, prob.weights, g[0], b[0], z)
+            amps.append({"z": z, "re": a.real, "im": a.imag})
+            print(f"amplitude z={z}: {a!r} ({time.time() - t0:.1f} s)", flush=True)
+        out["weighted_3reg_n30_amp_p1"] = {"gamma": g[0], "beta": b[0], "amplitudes": amps}
+        # the second layer's angles: |sin beta| > |cos beta|, the shifted factored form
+        amps2 = []
+        for z in zs[:4]:
+            a = oracle.amplitude_p1(n, prob.edges, prob.weights, g[1], b[1], z)
+            amps2.append({"z": z, "re": a.real, "im": a.imag})
+            print(f"amplitude (layer-2 angles) z={z}: {a!r} ({time.time() - t0:.1f} s)", flush=True)
+        out["weighted_3reg_n30_amp_p1_shifted"] = {"gamma": g[1], "beta": b[1], "amplitudes": amps2}
         json.dump(out, open(OUT, "w"), indent=1)
         return
     if "--only-max-cut" in sys.argv:

@@ -123,6 +123,34 @@ def test_n30_p10_c64_against_c128():
     assert 1 - f <= 1e-5
 
 
+# Element-wise at n = 30 in the benchmark's launch configuration (complex64:
+# the first pass, then one chunked pass pair), at depth 1, where the oracle sums
+# single amplitudes over the 2^30 basis states (stored; distinct under the
+# global flip, which fixes the exact state).  Errors relative to 2^(-n/2).
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("key", ["weighted_3reg_n30_amp_p1", "weighted_3reg_n30_amp_p1_shifted"])
+def test_n30_p1_amplitudes_match_oracle(prec, key):
+    d = _golden(key)
+    prob, _, _ = W.weighted_3reg_n30()
+    if prec == "c64":
+        assert q.qaoa_chunk_plan(prob.n, prec, 1, 128 << 20)[0] >= 1
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    buf = torch.empty(1 << prob.n, dtype=dt, device="cuda")
+    sim = q.Simulator(prob.n, prob.edges, prob.weights, prec)
+    try:
+        q.qaoa_bind_state(sim.handle, buf)
+        sim.expect([d["gamma"]], [d["beta"]])
+        torch.cuda.synchronize()
+        zs = torch.tensor([a["z"] for a in d["amplitudes"]], dtype=torch.int64, device="cuda")
+        got = buf[zs].cpu().numpy().astype(np.complex128)
+    finally:
+        sim.close()
+    want = np.array([complex(a["re"], a["im"]) for a in d["amplitudes"]])
+    err = float(np.max(np.abs(got - want))) / 2.0 ** (-prob.n / 2)
+    print(f"n=30 p=1 {prec} {key}: max |dpsi| / 2^-15 = {err:.3e}")
+    assert err <= (1e-10 if prec == "c128" else 1e-4)
+
+
 # The complex64 default at n=30 runs each (low set, high set) pass pair chunk
 # by chunk over three streams; whole passes must give bitwise the same state
 # and <C> (every tile computes the same arithmetic either way).

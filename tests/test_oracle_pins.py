@@ -150,6 +150,22 @@ def test_state_matches_dense_matrix_exponential(seed, n, weighted, p):
     assert nrm == pytest.approx(1.0, abs=1e-13)
 
 
+# One amplitude of the depth-1 state as a sum over basis states (used for the
+# element-wise checks at n = 30, where no state vector fits the oracle): every
+# amplitude against the dense matrix exponentials, for angles in all four
+# quadrants of beta (sin and cos of either sign) and both graph kinds.
+@pytest.mark.parametrize("seed,n,kind,weighted", [(46, 3, "complete", True), (47, 5, "gnp", False),
+                                                  (48, 8, "gnp", True), (49, 6, "3reg", False)])
+def test_single_amplitude_p1_matches_dense_matrix_exponential(seed, n, kind, weighted):
+    pr = _rand_problem(seed, n, kind, weighted)
+    for g, b in ((0.83, 1.27), (0.4, 0.2), (2.1, 2.9), (-0.7, -1.9)):
+        ref = oracle.dense_evolve(n, pr.edges, pr.weights, [g], [b])
+        got = np.array([oracle.amplitude_p1(n, pr.edges, pr.weights, g, b, z) for z in range(1 << n)])
+        assert np.max(np.abs(got - ref)) < 1e-13
+    with pytest.raises(ValueError):
+        oracle.amplitude_p1(n, pr.edges, pr.weights, 0.1, 0.2, 1 << n)
+
+
 def test_cost_diagonal_matches_pauli_kronecker():
     pr = _rand_problem(45, 9, "gnp", True)
     assert np.allclose(oracle.cut_table(9, pr.edges, pr.weights),
@@ -314,12 +330,17 @@ def _battery(lib):
             fails.append("alg3")
         g, b = W.uniform_angles(2, W.SplitMix64(3))
         pw = _rand_problem(12, 6, "gnp", True)
+        pw5 = _rand_problem(13, 5, "gnp", True)
         psi = oracle.evolve(6, pw.edges, pw.weights, g, b, lib=lib)
         if np.max(np.abs(psi - oracle.dense_evolve(6, pw.edges, pw.weights, g, b))) > 1e-12:
             fails.append("dense")
         ex, nrm = oracle.run_expect(8, pr.edges, None, g * 0, b, lib=lib)
         if abs(ex - pr.num_edges / 2) > 1e-12 or abs(nrm - 1) > 1e-12:
             fails.append("special")
+        ref1 = oracle.dense_evolve(5, pw5.edges, pw5.weights, [0.83], [2.1])
+        amps = [oracle.amplitude_p1(5, pw5.edges, pw5.weights, 0.83, 2.1, z, lib=lib) for z in range(32)]
+        if np.max(np.abs(np.array(amps) - ref1)) > 1e-12:
+            fails.append("amplitude")
         ex, dg, db = oracle.grad(6, pw.edges, pw.weights, g, b, lib=lib)
         fg, fb = oracle.grad_fd(6, pw.edges, pw.weights, g, b, lib=lib)
         if max(np.max(np.abs(dg - fg)), np.max(np.abs(db - fb))) > 1e-6:
@@ -341,6 +362,10 @@ MUTANTS = [
     ("adjoint conjugation", "ks_add(&s, lam[2 * z] * phi[2 * y + 1] - lam[2 * z + 1] * phi[2 * y]);",
      "ks_add(&s, lam[2 * z] * phi[2 * y + 1] + lam[2 * z + 1] * phi[2 * y]);"),
     ("mixer undo direction", "apply_rx(N, phi, q, -beta[l]);", "apply_rx(N, phi, q, beta[l]);"),
+    ("amplitude: +i sin off the diagonal", "pi[4] = {0.0, -1.0, 0.0, 1.0}", "pi[4] = {0.0, 1.0, 0.0, -1.0}"),
+    ("amplitude: distance from x alone", "__builtin_popcountll((uint64_t)(x ^ z))", "__builtin_popcountll((uint64_t)x)"),
+    ("amplitude: cos and sin powers swapped", "pow(cb, n - d) * pow(sb, d)", "pow(sb, n - d) * pow(cb, d)"),
+    ("amplitude: cost phase sign", "const double er = cos(th), ei = -sin(th);", "const double er = cos(th), ei = sin(th);"),
 ]
 
 
