@@ -16,8 +16,11 @@ inputs of workloads/:
                    under the global flip), each summed over the 2^30 basis states
                    (oracle.amplitude_p1); _shifted: the same at the second layer's
                    angles (|sin beta| > |cos beta|), four indices
+  gnp_n26_state_samples, weighted_3reg_n30_state_samples  16 amplitudes each of
+                   the full-depth oracle states of those two workloads, at seeded
+                   indices distinct under the global flip
 
-Usage: python tests/golden/make_golden.py [--skip-n30] [--only-max-cut] [--only-fd] [--only-amp]
+Usage: python tests/golden/make_golden.py [--skip-n30] [--only-max-cut] [--only-fd] [--only-amp] [--only-state-samples]
 (n = 30 needs ~24 GiB RAM)
 """
 from __future__ import annotations
@@ -50,6 +53,29 @@ def main():
             print(f"grad_gnp_n24 FD set {i} ({time.time() - t0:.1f} s)", flush=True)
         out["grad_gnp_n24_fd"] = {"h": 1e-6, "sets": sets}
         json.dump(out, open(OUT, "w"), indent=1)
+        return
+    if "--only-state-samples" in sys.argv:
+        # amplitudes of the full oracle evolution at seeded indices (distinct under
+        # the global flip): the n=26 p=4 and n=30 p=10 workloads at their full depth
+        # (n = 30 holds the whole FP64 state: ~24 GiB)
+        for key, make in (("gnp_n26_state_samples", W.gnp_n26), ("weighted_3reg_n30_state_samples", W.weighted_3reg_n30)):
+            prob, g, b = make()
+            n = prob.n
+            t0 = time.time()
+            psi = oracle.evolve(n, prob.edges, prob.weights, g, b)
+            rng = W.SplitMix64(4242 + n)
+            zs, seen = [], set()
+            while len(zs) < 16:
+                z = rng.next_u64() % (1 << n)
+                if z in seen or ((1 << n) - 1 - z) in seen:
+                    continue
+                seen.add(z)
+                zs.append(z)
+            out[key] = {"p": len(g), "amplitudes": [{"z": z, "re": float(psi[z].real), "im": float(psi[z].imag)}
+                                                    for z in zs]}
+            del psi
+            print(f"{key}: 16 amplitudes ({time.time() - t0:.1f} s)", flush=True)
+            json.dump(out, open(OUT, "w"), indent=1)
         return
     if "--only-amp" in sys.argv:
         prob, g, b = W.weighted_3reg_n30()

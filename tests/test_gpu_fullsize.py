@@ -151,6 +151,33 @@ def test_n30_p1_amplitudes_match_oracle(prec, key):
     assert err <= (1e-10 if prec == "c128" else 1e-4)
 
 
+# Element-wise at full depth: 16 stored amplitudes of the oracle's complete FP64
+# evolution of the n=26 p=4 and n=30 p=10 workloads (indices distinct under the
+# global flip), against the library's default launch configuration (complex64:
+# chunked pass pairs).  Errors relative to 2^(-n/2).
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("key", ["gnp_n26_state_samples", "weighted_3reg_n30_state_samples"])
+def test_full_depth_state_samples_match_oracle(prec, key):
+    d = _golden(key)
+    prob, g, b = (W.gnp_n26 if key.startswith("gnp_n26") else W.weighted_3reg_n30)()
+    assert len(g) == d["p"]
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    buf = torch.empty(1 << prob.n, dtype=dt, device="cuda")
+    sim = q.Simulator(prob.n, prob.edges, prob.weights, prec)
+    try:
+        q.qaoa_bind_state(sim.handle, buf)
+        sim.expect(g, b)
+        torch.cuda.synchronize()
+        zs = torch.tensor([a["z"] for a in d["amplitudes"]], dtype=torch.int64, device="cuda")
+        got = buf[zs].cpu().numpy().astype(np.complex128)
+    finally:
+        sim.close()
+    want = np.array([complex(a["re"], a["im"]) for a in d["amplitudes"]])
+    err = float(np.max(np.abs(got - want))) / 2.0 ** (-prob.n / 2)
+    print(f"{key} {prec}: max |dpsi| / 2^(-n/2) = {err:.3e}")
+    assert err <= (1e-10 if prec == "c128" else 1e-4)
+
+
 # The complex64 default at n=30 runs each (low set, high set) pass pair chunk
 # by chunk over three streams; whole passes must give bitwise the same state
 # and <C> (every tile computes the same arithmetic either way).
