@@ -231,7 +231,7 @@ def test_n24_gradients_all_64_sets(prec):
             err = max(np.max(np.abs(dg - r["dgamma"])), np.max(np.abs(db - r["dbeta"])))
             worst = max(worst, err)
             assert abs(e - r["expect"]) <= _tol(prec, m)
-            assert err <= (1e-9 if prec == "c128" else 1e-3) * m
+            assert err <= (1e-9 if prec == "c128" else 1e-4) * m
     finally:
         sim.close()
     print(f"n=24 p=8 {prec}: worst gradient error over 64 sets {worst:.3e} (|E| = {m})")
