@@ -246,7 +246,7 @@ int qaoa_plan_info(qaoa_ctx *ctx, int p, int *passes, int *sets, int *sizes, int
  * each tile bit, gpos[0..n-K): the memory bit of each tile-index bit, and
  * (if not NULL) the same index map as runs, gmask[0..12) / gshift[0..12):
  * base offset of tile g = OR over r of (g & gmask[r]) << gshift[r].  tpos
- * needs 16 entries, gpos 64.  QAOA_EINVAL for n outside [1, 34] or a set
+ * needs 16 entries, gpos 64.  QAOA_EINVAL for n outside [1, 35] or a set
  * the plan does not have. */
 int qaoa_tile_map(int n, int prec, int set, int *k_out, int8_t *tpos, int8_t *gpos, uint64_t *gmask,
                   int8_t *gshift);
@@ -272,7 +272,7 @@ const char *qaoa_last_error(void);
  * its result is bitwise the same alone or in a mix.
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int n;                  /* 1 <= n <= 34 */
+  int n;                  /* 1 <= n <= 35 */
   int num_edges;
   const int32_t *edges;   /* as in qaoa_create */
   const double *weights;  /* NULL = unweighted */

@@ -58,7 +58,7 @@ static void ks_add(ksum *k, double x) {
 static double ks_val(const ksum *k) { return k->s + k->c; }
 
 static int check_graph(int n, int m, const int32_t *edges, const double *w) {
-    if (n < 1 || n > 34 || m < 0) return -1;
+    if (n < 1 || n > 35 || m < 0) return -1;
     if (m > 0 && !edges) return -1;
     for (int e = 0; e < m; ++e) {
         int u = edges[2 * e], v = edges[2 * e + 1];
@@ -173,7 +173,7 @@ static void chunked_sums(int64_t N, const double *psi, const double *cut,
 
 /* <C> and norm of a given state (interleaved complex128) against a cut table. */
 int oracle_expect(int n, const double *psi, const double *cut, double *e_out, double *norm_out) {
-    if (n < 1 || n > 34 || !psi || !cut) return -1;
+    if (n < 1 || n > 35 || !psi || !cut) return -1;
     chunked_sums((int64_t)1 << n, psi, cut, e_out, norm_out);
     return 0;
 }
@@ -279,7 +279,7 @@ int oracle_grad(int n, int m, const int32_t *edges, const double *w, int p,
 
 /* F = |<a|b>|^2 / (<a|a><b|b>), interleaved complex128 inputs. */
 int oracle_fidelity(int n, const double *a, const double *b, double *f_out) {
-    if (n < 1 || n > 34 || !a || !b || !f_out) return -1;
+    if (n < 1 || n > 35 || !a || !b || !f_out) return -1;
     const int64_t N = (int64_t)1 << n;
     int64_t nch = (N + CHUNK - 1) / CHUNK;
     double *pr = (double *)malloc(sizeof(double) * nch);

@@ -427,7 +427,8 @@ int qaoa_max_qubits(int prec, int with_grad) {
   const size_t margin = (size_t)256 << 20;
   int best = 0;
   for (int n = 1; n <= kMaxN; ++n) {
-    const size_t need = ((size_t)1 << n) * elem * (with_grad ? 2 : 1) + margin;
+    const size_t need = ((size_t)1 << n) * elem * (with_grad ? 2 : 1) + tile_cut_doubles(n, prec) * sizeof(double) +
+                        margin;
     if (need <= fr) best = n;
   }
   return best;

@@ -2,7 +2,7 @@
 // tests compile it on its own).
 //
 // A HIP launch may hold at most 2^32 - 1 work-items per grid dimension, and a
-// state of 2^34 amplitudes has more items than that.  Such sweeps therefore
+// state of 2^33 or more amplitudes has more items than that.  Such sweeps therefore
 // run grid-stride: the grid is capped at kMaxSweepBlocks workgroups, and each
 // workgroup walks chunks blockIdx.x, blockIdx.x + gridDim.x, ... until the
 // chunk count is reached.

@@ -26,7 +26,7 @@ enum : int32_t {
 
 constexpr int kMaxLogR = 5;
 constexpr int kMaxRounds = 4;
-constexpr int kMaxN = 34;
+constexpr int kMaxN = 35;   // a complex64 state of 2^35 amplitudes is 256 GiB
 constexpr int kMaxThreads = 256;
 constexpr int kMaxTileBits = 16;
 

@@ -18,7 +18,7 @@ def test_library_exports_every_header_symbol():
 
 @pytest.mark.parametrize("n,edges,w,prec", [
     (0, [[0, 1]], None, "c128"),            # n out of range
-    (35, [[0, 1]], None, "c128"),
+    (36, [[0, 1]], None, "c128"),
     (4, [[0, 4]], None, "c128"),             # vertex out of range
     (4, [[2, 2]], None, "c64"),              # self loop
     (4, [[0, 1], [1, 0]], None, "c64"),      # duplicate pair
@@ -64,7 +64,7 @@ def test_calls_out_of_order_and_bad_arguments():
 
 
 @pytest.mark.parametrize("prec,kmax,pas", [("c64", 13, 4), ("c128", 12, 3)])
-@pytest.mark.parametrize("n", [1, 3, 7, 12, 13, 14, 17, 22, 23, 26, 30, 34])
+@pytest.mark.parametrize("n", [1, 3, 7, 12, 13, 14, 17, 22, 23, 26, 30, 34, 35])
 def test_plan_covers_every_qubit_once(prec, kmax, pas, n):
     h = q.qaoa_create(n, [], None, prec)
     try:

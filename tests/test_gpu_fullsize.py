@@ -258,9 +258,10 @@ def test_n24_gradient_vs_central_differences():
         sim.close()
 
 
-@pytest.mark.parametrize("prec,n", [("c64", 32), ("c128", 31)])
+@pytest.mark.parametrize("prec,n", [("c64", 32), ("c128", 31), ("c64", 35)])
 def test_beyond_2_31_amplitudes_p1_closed_form(prec, n):
-    """32 GiB states: tile indices and byte offsets beyond 32 bits."""
+    """16-256 GiB states: tile indices and byte offsets beyond 32 bits, up to the largest
+    accepted size (complex64 n = 35, four qubit sets)."""
     if q.qaoa_max_qubits(prec) < n:
         pytest.skip("not enough free device memory")
     # 3-regular on an even vertex count (odd n: one isolated vertex more)

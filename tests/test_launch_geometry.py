@@ -1,7 +1,7 @@
 """Launch geometry of the whole-state sweeps, checked on the CPU.
 
 HIP allows at most 2^32 - 1 work-items per grid dimension; the state of the
-largest accepted size (n = 34) has 2^34 amplitudes.  The sweeps that touch
+largest accepted size (n = 35) has 2^35 amplitudes.  The sweeps that touch
 every amplitude or pair (the gate-by-gate circuit and the in-place reversal
 of a complemented bound state) therefore run grid-stride on a capped grid.
 This compiles the library's geometry header with the host compiler and
@@ -39,7 +39,7 @@ static int check(const char* what, int n, int64_t items, int64_t per_chunk, int6
 
 int main() {
   int bad = 0;
-  for (int n = 1; n <= 34; ++n) {
+  for (int n = 1; n <= 35; ++n) {
     const SweepGrids g = sweep_grids(n);
     const int64_t N = int64_t(1) << n;
     bad += check("gate_full", n, N, 256 * kSweepItems, g.gate_full);

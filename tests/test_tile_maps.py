@@ -96,7 +96,7 @@ def test_high_sets_deal_qubits_round_robin(prec):
 
 
 def test_tile_map_rejects_bad_arguments():
-    for args in ((0, "c64", 0), (35, "c64", 0), (30, "c64", 3), (30, "c64", -1), (12, "c128", 1)):
+    for args in ((0, "c64", 0), (36, "c64", 0), (30, "c64", 3), (30, "c64", -1), (12, "c128", 1)):
         with pytest.raises(q.QAOAError) as ei:
             q.qaoa_tile_map(*args)
         assert ei.value.code == q.QAOA_EINVAL
