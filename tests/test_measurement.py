@@ -99,3 +99,24 @@ def test_counter_summary_scales_by_the_copy_kernel(tmp_path, capsys):
     (tmp_path / "c.md").write_text(out)
     t, src = bench.pmc_traffic(str(tmp_path / "c.md"), "k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>")
     assert t == pytest.approx((900.0 * 2 + 2000.0) * 1024, rel=1e-6)
+
+
+def test_stats_summary_splits_launch_sizes(tmp_path, capsys):
+    """Whole-pass and chunk launches of one kernel get separate averages, so the
+    per-launch figure the benchmark reports can be found in the summary."""
+    import paper_2312_03019_amd.profile_summary as ps
+    mrg = "void qaoa::k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>(qaoa::PassDesc const*, int, qaoa::LaunchMap)"
+    with open(tmp_path / "b_kernel_stats.csv", "w") as f:
+        f.write('"Name","Calls","TotalDurationNs","AverageNs","Percentage","MinNs","MaxNs"\n')
+        f.write(f'"{mrg}",4,8300000,2075000,90.0,100000,4000000\n')
+    with open(tmp_path / "b_kernel_trace.csv", "w") as f:
+        f.write('"Kernel_Name","Grid_Size_X","Workgroup_Size_X","Start_Timestamp","End_Timestamp"\n')
+        for start, dur, wgs in ((0, 4000000, 131072), (5000000, 4000000, 131072), (10000000, 100000, 2048),
+                                (11000000, 200000, 2048)):
+            f.write(f'"{mrg}",{wgs * 256},256,{start},{start + dur}\n')
+    ps.stats(argparse.Namespace(dir=str(tmp_path), prefix="b", cmd="synthetic"))
+    out = capsys.readouterr().out
+    fields = dict(re.findall(r"^- (avg_ms [^:]+): (\S+)$", out, re.M))
+    assert float(fields["avg_ms k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1> x131072"]) == pytest.approx(4.0)
+    assert float(fields["avg_ms k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1> x2048"]) == pytest.approx(0.15)
+    assert float(fields["avg_ms k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>"]) == pytest.approx(2.075)
