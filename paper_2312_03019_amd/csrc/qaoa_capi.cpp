@@ -182,8 +182,7 @@ static int launch_pair_chunks(qaoa_ctx* c, const RunImage& img, const PassDesc* 
   for (int64_t k = 0; k < nch; ++k) {
     hipStream_t s1 = p1s[k & 1], s2 = p2s[k & 1];
     const LaunchMap la = chunk_launch_map(list[a].map, nfree, fixed, k);
-    HIPCHK(launch_pass(prec, false, logr, list[a].shape, dlist + a, 1, per, nthreads, s1, la));
-    HIPCHK(hipEventRecord(c->chunk_ev[k], s1));
+    HIPCHK(launch_pass(prec, false, logr, list[a].shape, dlist + a, 1, per, nthreads, s1, la, c->chunk_ev[k]));
     HIPCHK(hipStreamWaitEvent(s2, c->chunk_ev[k], 0));
     if (c->profiling && k == 0) HIPCHK(hipEventRecord(c->ev[2 * b], s2));
     const LaunchMap lb = chunk_launch_map(list[b].map, nfree, fixed, k);

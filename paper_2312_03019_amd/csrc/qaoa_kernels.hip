@@ -23,6 +23,7 @@
 // cut when that bit flips alone; C(z0 ^ J) = C(z0) + sum_{k in J} d_k + RT[J]
 // with RT the cut among the register vertices (a per-pass table).  The
 // phase is then a product tree of 1 + LOGR complex exponentials.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -1088,14 +1089,23 @@ __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ s_, flo
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// A pass launch; with `done` the launch itself marks that event when the kernel
+// completes (no separate marker on the queue), for a wait on another stream.
+template <typename K>
+static void launch_fwd_kernel(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t done, const PassDesc* d,
+                              int ndesc, const LaunchMap& lm) {
+  if (done) hipExtLaunchKernelGGL(kernel, grid, block, 0, st, nullptr, done, 0, d, ndesc, lm);
+  else hipLaunchKernelGGL(kernel, grid, block, 0, st, d, ndesc, lm);
+}
+
 template <typename R, int KB, int LOGR>
 static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, const LaunchMap& lm, dim3 grid, dim3 block,
-                              hipStream_t st) {
+                              hipStream_t st, hipEvent_t done) {
   constexpr int HALF = 1;   // full-width tiles move through half the LDS
   switch (shape) {
 #define QAOA_FWD(NRC, CODE, NSC, PHM, GEN, EXP)                                                              \
   case NRC * 8 + CODE:                                                                                      \
-    hipLaunchKernelGGL((k_fwd<R, LOGR, KB, NRC, NSC, PHM, GEN, EXP, HALF>), grid, block, 0, st, d, ndesc, lm); \
+    launch_fwd_kernel(k_fwd<R, LOGR, KB, NRC, NSC, PHM, GEN, EXP, HALF>, grid, block, st, done, d, ndesc, lm);  \
     return;
 #define QAOA_FWD_NR(NRC)                                      \
   QAOA_FWD(NRC, kShapeFirst, 1, 1, 1, 0)                      \
@@ -1115,14 +1125,14 @@ static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, const Lau
 #undef QAOA_FWD_NR
 #undef QAOA_FWD
     default:
-      hipLaunchKernelGGL((k_fwd<R, LOGR, KB, 0, 0, -1, -1, -1, 0>), grid, block, 0, st, d, ndesc, lm);
+      launch_fwd_kernel(k_fwd<R, LOGR, KB, 0, 0, -1, -1, -1, 0>, grid, block, st, done, d, ndesc, lm);
   }
 }
 
 template <typename R, int KB>
 static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDesc* d, int ndesc, const LaunchMap& lm,
-                                int64_t nblocks,
-                                int nthreads, hipStream_t st) {
+                                int64_t nblocks, int nthreads, hipStream_t st, hipEvent_t done) {
+  if (backward && done) return hipErrorInvalidValue;   // completion events: forward passes only
   const dim3 grid((unsigned)nblocks), block((unsigned)nthreads);
   constexpr int LMAX = sizeof(R) == 4 ? kLogRC64 : kLogRC128;
   if (logr < 1 || logr > LMAX) return hipErrorInvalidValue;
@@ -1158,11 +1168,11 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
     return hipGetLastError();
   }
   if (logr == LMAX) {
-    launch_fwd_shaped<R, KB, LMAX>(shape, d, ndesc, lm, grid, block, st);
+    launch_fwd_shaped<R, KB, LMAX>(shape, d, ndesc, lm, grid, block, st, done);
     return hipGetLastError();
   }
 #define QAOA_GEN(LR) \
-  if (logr == LR) hipLaunchKernelGGL((k_fwd<R, LR, KB, 0, 0, -1, -1, -1, 0>), grid, block, 0, st, d, ndesc, lm);
+  if (logr == LR) launch_fwd_kernel(k_fwd<R, LR, KB, 0, 0, -1, -1, -1, 0>, grid, block, st, done, d, ndesc, lm);
   QAOA_GEN(1)
   QAOA_GEN(2)
   QAOA_GEN(3)
@@ -1172,10 +1182,10 @@ static hipError_t launch_pass_t(bool backward, int logr, int shape, const PassDe
 }
 
 hipError_t launch_pass(int prec, bool backward, int logr, int shape, const PassDesc* d, int ndesc, int64_t nblocks,
-                       int nthreads, hipStream_t st, const LaunchMap& lm) {
+                       int nthreads, hipStream_t st, const LaunchMap& lm, hipEvent_t done) {
   if (prec == 1)
-    return launch_pass_t<float, kTileBitsC64>(backward, logr, shape, d, ndesc, lm, nblocks, nthreads, st);
-  return launch_pass_t<double, kTileBitsC128>(backward, logr, shape, d, ndesc, lm, nblocks, nthreads, st);
+    return launch_pass_t<float, kTileBitsC64>(backward, logr, shape, d, ndesc, lm, nblocks, nthreads, st, done);
+  return launch_pass_t<double, kTileBitsC128>(backward, logr, shape, d, ndesc, lm, nblocks, nthreads, st, done);
 }
 
 // Mirrors the specialisations launch_pass_t selects (same cases, same

@@ -30,8 +30,11 @@ enum : int {
 // share logr and (forward) shape.
 // lm: the launch's tile map (identity_launch() for every tile of the pass;
 // must be the identity when ndesc > 1).
+// done: if not null, the launch marks this event when its kernel completes (a
+// forward pass; no separate marker enters the queue).
 hipError_t launch_pass(int prec, bool backward, int logr, int shape, const PassDesc* d, int ndesc, int64_t nblocks,
-                       int nthreads, hipStream_t st, const LaunchMap& lm = identity_launch());
+                       int nthreads, hipStream_t st, const LaunchMap& lm = identity_launch(),
+                       hipEvent_t done = nullptr);
 // Name of the kernel launch_pass runs for these arguments, as the profiler
 // reports it without the parameter list (e.g. "k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>").
 void pass_kernel_name(int prec, bool backward, int logr, int shape, char* buf, size_t len);
