@@ -147,9 +147,10 @@ int check_angles(int p, const double* g, const double* b) {
 }
 
 // One forward pass pair (passes a and a + 1) chunk by chunk: chunk k's first
-// pass on a first-pass stream, its second pass on a second-pass stream once an
-// event marks that chunk written, while the first-pass streams go on with the
-// next chunks.  First-pass streams: the
+// pass on a first-pass stream, its second pass on a second-pass stream once the
+// first pass's launch has marked chunk k written (the launch's own completion
+// event: no marker packet between consecutive first-pass chunks), while the
+// first-pass streams go on with the next chunks.  First-pass streams: the
 // context stream (and xs[2] with four streams, alternating); second-pass
 // streams: xs[0] (and xs[1] with three or four, alternating).  The pair starts
 // after the context stream's earlier work and ends with all streams joined back
