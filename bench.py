@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QAOA layer amp-updates/s + HBM GB/s at n=30; served ⟨C⟩ req/s, p50/p99"
 HBM_PEAK_GBS = 8000.0
 # the library's default chunk size for pipelined pass pairs (complex64; complex128 runs whole passes)
-CHUNK_BYTES = {"c64": 128 << 20, "c128": 0}
+CHUNK_BYTES = {"c64": 128 << 20, "c128": 128 << 20}
 
 
 def parse():
@@ -594,7 +594,8 @@ def main():
                         "ms_per_step_with_pass_events": r128["t_prof"] * 1e3,
                         "hbm_gbps_all_passes": r128["launch_bytes_mean"] / (r128["launch_ms_mean"] * 1e-3) / 1e9,
                         "expect": r128["expect"], "kernels": r128["kernels"],
-                        "passes": [{k: r[k] for k in ("i", "set", "kernel", "ms", "gbps", "frac")} for r in r128["rows"]]}
+                        "passes": [{k: r[k] for k in ("i", "set", "kernel", "ms", "gbps", "frac")} for r in r128["rows"]],
+                        "chunked_pairs": r128.get("chunked")}
         line["c64_over_c128_speedup"] = r128["t"] / r64["t"]
         line["delta_expect_c64_c128"] = r64["expect"] - r128["expect"]
         line["one_minus_fidelity_c64_c128"] = 1.0 - res["fidelity_c64_c128"]

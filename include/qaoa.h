@@ -28,6 +28,10 @@
  *     caller lends a buffer with qaoa_bind_state.
  *   - Threads: one context must not be used from two threads at once (the
  *     second caller gets QAOA_ESTATE).  A server handle is thread-safe.
+ *   - Streams: a context runs on the stream given to qaoa_bind_stream, else
+ *     on a library stream that all unbound contexts on the device share;
+ *     chunked pass pairs add up to three more library streams per device,
+ *     shared the same way.  Library streams live until the process ends.
  *   - Device errors (HIP) are reported as QAOA_EDEVICE with the HIP message.
  */
 #ifndef QAOA_H
@@ -206,9 +210,9 @@ int qaoa_pass_times(qaoa_ctx *ctx, float *ms, double *bytes, int max, int *count
  * still cached.  The result is bitwise the same as unchunked.  chunk_bytes =
  * 0 turns chunking off.  streams (2, 3 or 4, else QAOA_EINVAL): 2 runs the
  * high-set chunks on one extra stream, 3 alternates them over two, 4 also
- * alternates the low-set chunks over two streams.  Defaults: complex64, 128
- * MiB chunks for states from 512 MiB (n >= 26) on three streams; complex128,
- * off. */
+ * alternates the low-set chunks over two streams.  Defaults: 128 MiB chunks
+ * for states from 512 MiB (complex64 n >= 26, complex128 n >= 25) on three
+ * streams. */
 int qaoa_set_chunking(qaoa_ctx *ctx, size_t chunk_bytes, size_t min_state_bytes, int streams);
 
 /* Inspection of the chunked pass pairs, no GPU needed (tests).  Chunk bits

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -30,7 +31,6 @@ struct qaoa_ctx {
   int device = 0;
   bool dev_ready = false;
   hipStream_t stream = nullptr;
-  bool own_stream = false;
   bool stream_bound = false;
   void* psi = nullptr;
   bool own_psi = false;
@@ -54,7 +54,7 @@ struct qaoa_ctx {
   size_t chunk_bytes = 0;
   size_t chunk_min_state = 0;   // chunking only for states at least this large
   int chunk_streams = 2;               // 2: P2 chunks on one extra stream; 3: on two; 4: P1 on two as well
-  hipStream_t xs[3] = {nullptr, nullptr, nullptr};
+  hipStream_t xs[3] = {nullptr, nullptr, nullptr};   // the device's library streams 1..3
   std::vector<hipEvent_t> chunk_ev;
   hipEvent_t join_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool upload_pending = false;
@@ -109,14 +109,35 @@ int grow_host(void** p, size_t* cap, size_t need, qaoa_ctx* c) {
   return QAOA_OK;
 }
 
+// Library streams, shared by every context on a device and kept until the
+// process ends: stream 0 is the stream of contexts not bound to a caller's
+// stream, 1..3 are the extra streams of chunked pass pairs.  A device has a
+// few hardware queues, which its streams share in turn; with streams of their
+// own per context, a context's second-pass stream can land on the queue of its
+// own first-pass chain, which serialises the pair (complex128 n = 30 with a
+// complex64 context alive: 144 ms per run with private extra streams, 115 ms
+// with shared ones, as alone).  Contexts that run at once on different threads
+// then queue their launches behind each other on these streams: still correct
+// (every wait is on the context's own events), not concurrent.
+static hipError_t device_streams(int device, int count, hipStream_t* out) {
+  static std::mutex mu;
+  static std::map<int, std::vector<hipStream_t>> pool;
+  std::lock_guard<std::mutex> lock(mu);
+  std::vector<hipStream_t>& v = pool[device];
+  while ((int)v.size() < count) {
+    hipStream_t st = nullptr;
+    const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);   // default priority
+    if (e != hipSuccess) return e;
+    v.push_back(st);
+  }
+  for (int i = 0; i < count; ++i) out[i] = v[i];
+  return hipSuccess;
+}
+
 int ensure_device(qaoa_ctx* c) {
   if (c->dev_ready) return QAOA_OK;
   HIPCHK(hipGetDevice(&c->device));
-  if (!c->stream && !c->stream_bound) {
-    // default: a private non-blocking stream at default priority
-    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    c->own_stream = true;
-  }
+  if (!c->stream && !c->stream_bound) HIPCHK(device_streams(c->device, 1, &c->stream));   // the library stream
   const size_t gb = dev_graph_bytes(c->hg);
   HIPCHK(hipMalloc(&c->dgraph, gb));
   std::vector<char> img(gb);
@@ -165,8 +186,11 @@ static int launch_pair_chunks(qaoa_ctx* c, const RunImage& img, const PassDesc* 
   const int64_t nch = (int64_t)1 << img.chunk_bits, per = ntiles >> img.chunk_bits;
   const int S = c->chunk_streams;
   const int nx = S - 1;
-  for (int x = 0; x < nx; ++x)
-    if (!c->xs[x]) HIPCHK(hipStreamCreateWithFlags(&c->xs[x], hipStreamNonBlocking));
+  if (!c->xs[nx - 1]) {
+    hipStream_t all[4];
+    HIPCHK(device_streams(c->device, nx + 1, all));
+    for (int x = 0; x < nx; ++x) c->xs[x] = all[x + 1];
+  }
   while ((int64_t)c->chunk_ev.size() < nch) {
     hipEvent_t e;
     HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -384,14 +408,13 @@ int qaoa_create(int n, int num_edges, const int32_t* edges, const double* weight
   c->hg = std::move(hg);
   c->prec = prec;
   c->state_bytes = ((size_t)1 << n) * prec_cfg(prec).elem;
-  if (prec == QAOA_C64) {
-    // measured on three-set plans: n = 30 runs 8% faster with 128 MiB chunks
-    // and the high-set chunks alternating over two streams (3% at n = 26, 28);
-    // complex128 runs were slower chunked at every chunk size tried
-    c->chunk_bytes = (size_t)128 << 20;
-    c->chunk_min_state = (size_t)512 << 20;
-    c->chunk_streams = 3;
-  }
+  // measured on three-set plans with 128 MiB chunks and the high-set chunks
+  // alternating over two streams: complex64 n = 30 runs 10% faster chunked
+  // (3% at n = 26, 28), complex128 n = 30 10% (9% at n = 26, 28); from 512
+  // MiB states on, smaller ones run faster whole
+  c->chunk_bytes = (size_t)128 << 20;
+  c->chunk_min_state = (size_t)512 << 20;
+  c->chunk_streams = 3;
   *out = c;
   return QAOA_OK;
 }
@@ -409,13 +432,10 @@ void qaoa_destroy(qaoa_ctx* c) {
   for (hipEvent_t e : c->chunk_ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->join_ev)
     if (e) (void)hipEventDestroy(e);
-  for (hipStream_t x : c->xs)
-    if (x) (void)hipStreamDestroy(x);
   if (c->host_img) (void)hipHostFree(c->host_img);
   if (c->host_out) (void)hipHostFree(c->host_out);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
   for (auto e : c->ev) (void)hipEventDestroy(e);
-  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -687,9 +707,7 @@ int qaoa_bind_stream(qaoa_ctx* c, void* hip_stream) {
     return c ? QAOA_ESTATE : QAOA_EINVAL;
   }
   if (c->dev_ready) HIPCHK(hipStreamSynchronize(c->stream));
-  if (c->own_stream && c->stream) HIPCHK(hipStreamDestroy(c->stream));
   c->stream = (hipStream_t)hip_stream;
-  c->own_stream = false;
   c->stream_bound = true;
   return QAOA_OK;
 }

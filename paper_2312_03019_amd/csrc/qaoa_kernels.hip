@@ -182,17 +182,24 @@ __device__ __forceinline__ void store_tile(const cx<R> (&v)[1 << LOGR], QGLOBAL 
 
 // Cache policy and occupancy per pass shape, as measured on the n = 30 plans
 // (complex64 and complex128, 8 / 16 GiB): the streaming (non-temporal)
-// policy pays for the passes over high-set tiles and for every complex128
-// pass, not for the complex64 low-set passes, whose contiguous tiles stream
-// better with the default policy and four workgroups per CU.  The two-round
-// merged complex64 pass runs four workgroups per CU as well (127 VGPRs).
+// policy pays for the passes over high-set tiles and for the complex128
+// passes launched whole.  The plain low-set pass (complex64: three rounds;
+// complex128: four, a shape only chunked pass pairs use) takes the default
+// policy, so the chunk it writes is still cached when the high-set pass
+// reads it (complex64 contiguous tiles also stream better that way whole),
+// and runs four workgroups per CU.  The two-round merged complex64 pass runs
+// four workgroups per CU as well (127 VGPRs).
+template <typename R, int NRC, int NSC, int GEN, int EXP>
+constexpr bool low_single() {
+  return NSC == 1 && GEN == 0 && EXP == 0 && NRC == (sizeof(R) == 4 ? 3 : 4);
+}
 template <typename R, int NRC, int NSC, int GEN, int EXP>
 __device__ constexpr bool fwd_streaming() {
-  return sizeof(R) == 8 || GEN == 1 || EXP > 0 || NSC == 2;
+  return !low_single<R, NRC, NSC, GEN, EXP>() && (sizeof(R) == 8 || GEN == 1 || EXP > 0 || NSC == 2);
 }
 template <typename R, int NRC, int NSC, int GEN, int EXP, int HALF>
 constexpr int fwd_waves() {
-  return !HALF ? 2 : (sizeof(R) == 4 && ((NSC == 1 && GEN == 0 && EXP == 0 && NRC == 3) || (NSC == 2 && NRC == 2))) ? 4 : 3;
+  return !HALF ? 2 : (low_single<R, NRC, NSC, GEN, EXP>() || (sizeof(R) == 4 && NSC == 2 && NRC == 2)) ? 4 : 3;
 }
 template <typename R, int NRC, int NSC, int NOSTORE>
 __device__ constexpr bool bwd_streaming() {
@@ -1116,10 +1123,14 @@ static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, const Lau
     QAOA_FWD_NR(1)
     QAOA_FWD_NR(2)
     QAOA_FWD_NR(3)
-    // Four rounds (the complex128 low set): a merged pass would spill and a
-    // plain single pass is faster through the full LDS (it already streams at
-    // copy speed there), so those two take the generic kernel.
+    // Four rounds (the complex128 low set): a merged pass would spill.  A
+    // plain single pass launched whole takes the generic full-LDS kernel (it
+    // streams at copy speed there); chunked beside a high-set pass it takes
+    // this half-LDS kernel, since two full-LDS workgroups per CU leave too
+    // little LDS for the high-set chunk's workgroups.  The planner gives the
+    // shape only to chunked passes.
     QAOA_FWD(4, kShapeFirst, 1, 1, 1, 0)
+    QAOA_FWD(4, kShapeSingle, 1, 0, 0, 0)
     QAOA_FWD(4, kShapeLast, 1, 0, 0, 1)
     QAOA_FWD(4, kShapeLastLam, 1, 0, 0, 2)
 #undef QAOA_FWD_NR
@@ -1207,9 +1218,9 @@ void pass_kernel_name(int prec, bool backward, int logr, int shape, char* buf, s
     }
     return;
   }
-  bool shaped = logr == LMAX && (((code == kShapeFirst || code == kShapeLast || code == kShapeLastLam) && nrc >= 1 &&
-                                  nrc <= 4) ||
-                                 ((code == kShapeSingle || code == kShapeMerged) && nrc >= 1 && nrc <= 3));
+  bool shaped = logr == LMAX && (((code == kShapeFirst || code == kShapeSingle || code == kShapeLast ||
+                                   code == kShapeLastLam) && nrc >= 1 && nrc <= 4) ||
+                                 (code == kShapeMerged && nrc >= 1 && nrc <= 3));
   if (!shaped) {
     snprintf(buf, len, "k_fwd<%s, %d, %d, 0, 0, -1, -1, -1, 0>", R, logr, KB);
     return;

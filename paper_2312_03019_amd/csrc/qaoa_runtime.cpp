@@ -339,7 +339,9 @@ static SiteDesc make_site(const SetGeom& s, int round, int logr, const HostGraph
 // Compiled pass shapes exist for full-width tiles (K and LOGR at their
 // maxima), whose rounds follow the half-tile pattern: [K-LOGR, K), then each
 // LOGR-1 lower, the last clamped at 0.  Anything else takes the generic kernel.
-static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const SegDesc* segs) {
+// A four-round plain pass (the complex128 low set) is shaped only when it runs
+// chunked (`chunked`): whole, the generic full-LDS kernel is faster.
+static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const SegDesc* segs, bool chunked) {
   if (d.K != pc.kmax || logr != pc.logr_max || d.nrounds < 1 || d.nrounds > 4) return 0;
   for (int i = 0; i < d.nrounds; ++i)
     if (d.rb[i] != std::max(0, d.K - logr - i * (logr - 1))) return 0;
@@ -347,7 +349,7 @@ static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const S
   const bool ph0 = d.nseg >= 1 && segs[0].has_phase, ph1 = d.nseg >= 2 && segs[1].has_phase;
   int code = 0;
   if (d.nseg == 1 && gen && ph0 && !ex) code = kShapeFirst;
-  else if (d.nseg == 1 && !gen && !ph0 && !ex && d.nrounds <= 3) code = kShapeSingle;
+  else if (d.nseg == 1 && !gen && !ph0 && !ex && (d.nrounds <= 3 || chunked)) code = kShapeSingle;
   else if (d.nseg == 2 && !gen && !ph0 && ph1 && !ex && d.nrounds <= 3) code = kShapeMerged;
   else if (d.nseg == 1 && !gen && !ph0 && ex) code = lam ? kShapeLastLam : kShapeLast;
   return code ? d.nrounds * 8 + code : 0;
@@ -410,6 +412,7 @@ void build_run(const RunRequest& rq, RunImage* img) {
   const int NR = 1 << logr;
 
   *img = RunImage();
+  img->chunk_bits = chunk_plan(sets, sched, rq.p, state_bytes, rq.chunk_bytes, &img->pair_fixed);
   // site tables depend only on (set, round): build each once
   std::vector<std::array<SiteDesc, 2>> sites(sets.size());
   for (size_t k = 0; k < sets.size(); ++k) {
@@ -509,7 +512,8 @@ void build_run(const RunRequest& rq, RunImage* img) {
     if (ph_even || ps.expect) fflags |= PF_SITE0;
     if (ph_odd) fflags |= PF_SITE1;
     d.flags |= fflags;
-    d.shape = forward_shape(d, pc, logr, img->segs.data() + seg0);
+    const bool chunked = img->chunk_bits > 0 && (i & 1) && i + 1 < sched.size();   // first pass of a pair
+    d.shape = forward_shape(d, pc, logr, img->segs.data() + seg0, chunked);
     d.psi = rq.psi;
     d.lam = rq.lam;
     d.g = rq.g;
@@ -541,7 +545,6 @@ void build_run(const RunRequest& rq, RunImage* img) {
     }
   }
   img->complemented = (mode1_layers & 1) != 0;
-  img->chunk_bits = chunk_plan(sets, sched, rq.p, state_bytes, rq.chunk_bytes, &img->pair_fixed);
   if (rq.grad) {
     // Scalars of the factored adjoint sweep (SegDesc): walk the passes and
     // segments in the order the sweep undoes them, with the rounds of each

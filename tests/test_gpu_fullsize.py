@@ -123,8 +123,8 @@ def test_n30_p10_c64_against_c128():
     assert 1 - f <= 1e-5
 
 
-# Element-wise at n = 30 in the benchmark's launch configuration (complex64:
-# the first pass, then one chunked pass pair), at depth 1, where the oracle sums
+# Element-wise at n = 30 in the benchmark's launch configuration (the first
+# pass, then one chunked pass pair), at depth 1, where the oracle sums
 # single amplitudes over the 2^30 basis states (stored; distinct under the
 # global flip, which fixes the exact state).  Errors relative to 2^(-n/2).
 @pytest.mark.parametrize("prec", ["c64", "c128"])
@@ -132,8 +132,7 @@ def test_n30_p10_c64_against_c128():
 def test_n30_p1_amplitudes_match_oracle(prec, key):
     d = _golden(key)
     prob, _, _ = W.weighted_3reg_n30()
-    if prec == "c64":
-        assert q.qaoa_chunk_plan(prob.n, prec, 1, 128 << 20)[0] >= 1
+    assert q.qaoa_chunk_plan(prob.n, prec, 1, 128 << 20)[0] >= 1
     dt = torch.complex128 if prec == "c128" else torch.complex64
     buf = torch.empty(1 << prob.n, dtype=dt, device="cuda")
     sim = q.Simulator(prob.n, prob.edges, prob.weights, prec)
@@ -153,8 +152,8 @@ def test_n30_p1_amplitudes_match_oracle(prec, key):
 
 # Element-wise at full depth: 16 stored amplitudes of the oracle's complete FP64
 # evolution of the n=26 p=4 and n=30 p=10 workloads (indices distinct under the
-# global flip), against the library's default launch configuration (complex64:
-# chunked pass pairs).  Errors relative to 2^(-n/2).
+# global flip), against the library's default launch configuration (chunked
+# pass pairs).  Errors relative to 2^(-n/2).
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("key", ["gnp_n26_state_samples", "weighted_3reg_n30_state_samples"])
 def test_full_depth_state_samples_match_oracle(prec, key):
@@ -178,25 +177,29 @@ def test_full_depth_state_samples_match_oracle(prec, key):
     assert err <= (1e-10 if prec == "c128" else 1e-4)
 
 
-# The complex64 default at n=30 runs each (low set, high set) pass pair chunk
-# by chunk over three streams; whole passes must give bitwise the same state
-# and <C> (every tile computes the same arithmetic either way).
-def test_n30_p10_chunked_pairs_equal_whole_passes():
+# The default at n=30 runs each (low set, high set) pass pair chunk by chunk
+# over three streams (complex128: with a half-LDS low-set kernel that only
+# chunked runs use); whole passes must give bitwise the same state and <C>
+# (every tile computes the same arithmetic either way).
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_n30_p10_chunked_pairs_equal_whole_passes(prec):
     prob, g, b = W.weighted_3reg_n30()
-    dt = torch.complex64
+    dt = torch.complex128 if prec == "c128" else torch.complex64
     bufs, es = [], []
     for chunk in (128 << 20, 0):
         buf = torch.empty(1 << prob.n, dtype=dt, device="cuda")
-        sim = q.Simulator(prob.n, prob.edges, prob.weights, "c64")
+        sim = q.Simulator(prob.n, prob.edges, prob.weights, prec)
         q.qaoa_bind_state(sim.handle, buf)
         q.qaoa_set_chunking(sim.handle, chunk, 0, 3)
         es.append(sim.expect(g, b))
         sim.close()
         bufs.append(buf)
-    assert q.qaoa_chunk_plan(prob.n, "c64", len(g), 128 << 20)[0] == 6
+    assert q.qaoa_chunk_plan(prob.n, prec, len(g), 128 << 20)[0] == (6 if prec == "c64" else 7)
     torch.cuda.synchronize()
     assert es[0] == es[1]
     assert torch.equal(bufs[0], bufs[1])
+    del bufs
+    torch.cuda.empty_cache()
 
 
 def test_n26_config_both_precisions():

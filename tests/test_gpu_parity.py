@@ -298,3 +298,36 @@ def test_chunked_pairs_join_the_caller_stream(prec, n):
     st.synchronize()
     assert np.array_equal(snap.cpu().numpy(), want)
     sim.close()
+
+
+# The extra streams of chunked runs are shared by every context on the device:
+# two contexts whose chunked runs alternate (and a third created between them)
+# each still get bitwise their whole-pass result.
+def test_chunked_contexts_share_streams():
+    n64, n128 = 24, 23
+    p64, p128 = _prob(380, n64, "gnp", True, 0.3), _prob(381, n128, "gnp", True, 0.3)
+    g, b = [0.45, 1.1, 0.8], [0.3, 1.2, 0.5]
+    want = {}
+    for key, n, pr, prec in (("c64", n64, p64, "c64"), ("c128", n128, p128, "c128")):
+        s = q.Simulator(n, pr.edges, pr.weights, prec)
+        q.qaoa_set_chunking(s.handle, 0, 0)
+        want[key] = (s.expect(g, b), s.state())
+        s.close()
+    a = q.Simulator(n64, p64.edges, p64.weights, "c64")
+    c = q.Simulator(n128, p128.edges, p128.weights, "c128")
+    for s in (a, c):
+        q.qaoa_set_chunking(s.handle, 1 << 20, 0, 3)
+    try:
+        for rep in range(2):
+            ea = a.expect(g, b)
+            mid = q.Simulator(n64, p64.edges, p64.weights, "c64")
+            q.qaoa_set_chunking(mid.handle, 1 << 20, 0, 3)
+            em = mid.expect(g, b)
+            mid.close()
+            ec = c.expect(g, b)
+            assert ea == want["c64"][0] and em == want["c64"][0], rep
+            assert ec == want["c128"][0], rep
+            assert np.array_equal(a.state(), want["c64"][1]) and np.array_equal(c.state(), want["c128"][1]), rep
+    finally:
+        a.close()
+        c.close()
