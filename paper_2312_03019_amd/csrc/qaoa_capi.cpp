@@ -410,7 +410,7 @@ int qaoa_create(int n, int num_edges, const int32_t* edges, const double* weight
   c->state_bytes = ((size_t)1 << n) * prec_cfg(prec).elem;
   // measured on three-set plans with 128 MiB chunks and the high-set chunks
   // alternating over two streams: complex64 n = 30 runs 10% faster chunked
-  // (3% at n = 26, 28), complex128 n = 30 10% (9% at n = 26, 28); from 512
+  // (3% at n = 26, 28), complex128 n = 30 10% (8% at n = 26, 28); from 512
   // MiB states on, smaller ones run faster whole
   c->chunk_bytes = (size_t)128 << 20;
   c->chunk_min_state = (size_t)512 << 20;
