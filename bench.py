@@ -321,7 +321,7 @@ def grad_hbm_bench(q, torch, W, n=28, p=4, reps=3):
     return out
 
 
-def n26_bench(q, torch, W, steps=5):
+def n26_bench(q, torch, W, steps=20):
     """The precision comparison workload: G(26, 0.5) unweighted, p=4, complex64
     against complex128: time per run, speedup, <C> of each against the stored
     FP64 oracle value, and 1 - fidelity between the two final states."""
@@ -331,7 +331,7 @@ def n26_bench(q, torch, W, steps=5):
     sims = {}
     for prec in ("c64", "c128"):
         sim = q.Simulator(prob.n, prob.edges, None, prec)
-        t, e, nrm = time_plain(q, torch, sim, g, b, steps, 1)
+        t, e, nrm = time_plain(q, torch, sim, g, b, steps, 3)
         out[prec] = {"ms_per_run": t * 1e3, "expect": e, "abs_err_vs_oracle_over_E": abs(e - ref) / prob.num_edges,
                      "layer_amp_updates_per_s": len(g) * 2 ** prob.n / t}
         sims[prec] = sim
