@@ -331,3 +331,29 @@ def test_chunked_contexts_share_streams():
     finally:
         a.close()
         c.close()
+
+
+# Kernel choice for the complex128 low-set pass: the generic full-LDS kernel
+# when launched whole, the half-LDS four-round kernel only in chunked pairs
+# (and both give bitwise the same result, as the test above checks).
+def test_c128_low_set_kernel_by_launch_mode():
+    n = 23
+    pr = _prob(390, n, "gnp", True, 0.3)
+    g, b = [0.45, 1.1], [0.3, 1.2]
+    sim = q.Simulator(n, pr.edges, pr.weights, "c128")
+    try:
+        names = {}
+        for label, chunk in (("whole", 0), ("chunked", 1 << 20)):
+            q.qaoa_set_chunking(sim.handle, chunk, 0, 3)
+            sim.expect(g, b)
+            names[label] = [q.qaoa_pass_kernel(sim.handle, i) for i in range(2 * len(g) + 1)]
+        low = [i for i, (st, _) in enumerate(names["whole"]) if st == 0]
+        assert low == [1, 3]
+        for i in low:
+            assert names["whole"][i][1] == "k_fwd<double, 4, 12, 0, 0, -1, -1, -1, 0>"
+            assert names["chunked"][i][1] == "k_fwd<double, 4, 12, 4, 1, 0, 0, 0, 1>"
+        for i in range(2 * len(g) + 1):
+            if i not in low:
+                assert names["whole"][i] == names["chunked"][i]
+    finally:
+        sim.close()
