@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QAOA layer amp-updates/s + HBM GB/s at n=30; served ⟨C⟩ req/s, p50/p99"
 HBM_PEAK_GBS = 8000.0
-# the library's default chunk size for pipelined pass pairs (complex64; complex128 runs whole passes)
+# the library's default chunk size for pipelined pass pairs (both precisions)
 CHUNK_BYTES = {"c64": 128 << 20, "c128": 128 << 20}
 
 
@@ -528,7 +528,7 @@ def main():
     res = {}
     for prec in (["c64"] if a.no_c128 else ["c64", "c128"]):
         sim = q.Simulator(prob.n, prob.edges, prob.weights, prec, stream=stream)
-        # the default path (complex64: pass pairs pipelined over chunks) gives the headline,
+        # the default path (pass pairs pipelined over chunks) gives the headline,
         # timed without profiling events; the same runs again with HIP events around every
         # pass (pass pair) give the per-pass table and the pair spans
         t, e, nrm = time_plain(q, torch, sim, g, b, a.steps, a.warmup)
