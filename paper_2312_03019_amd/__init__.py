@@ -263,7 +263,7 @@ def qaoa_pass_times(ctx, max_passes: int = 4096):
     return np.array(ms[:k], dtype=np.float64), np.array(by[:k], dtype=np.float64)
 
 
-def qaoa_set_chunking(ctx, chunk_bytes: int, min_state_bytes: int = 512 << 20, streams: int = 2) -> None:
+def qaoa_set_chunking(ctx, chunk_bytes: int, min_state_bytes: int = 512 << 20, streams: int = 3) -> None:
     """Chunked pass pairs: chunks of at least chunk_bytes for states from min_state_bytes (0 = off),
     spread over `streams` streams (2, 3 or 4)."""
     _err(_lib.qaoa_set_chunking(ctx, int(chunk_bytes), int(min_state_bytes), int(streams)))
