@@ -188,7 +188,10 @@ __device__ __forceinline__ void store_tile(const cx<R> (&v)[1 << LOGR], QGLOBAL 
 // policy, so the chunk it writes is still cached when the high-set pass
 // reads it (complex64 contiguous tiles also stream better that way whole),
 // and runs four workgroups per CU.  The two-round merged complex64 pass runs
-// four workgroups per CU as well (127 VGPRs).
+// four workgroups per CU as well (127 VGPRs) when launched whole; its chunk
+// launches in a pass pair (HALF = 2) run three, which leaves the low-set chunk
+// beside it more of each CU (n = 30, three runs each: 59.06 / 59.43 / 59.45 ->
+// 58.70 / 59.14 / 59.22 ms per run; whole passes are faster at four).
 template <typename R, int NRC, int NSC, int GEN, int EXP>
 constexpr bool low_single() {
   return NSC == 1 && GEN == 0 && EXP == 0 && NRC == (sizeof(R) == 4 ? 3 : 4);
@@ -199,7 +202,7 @@ __device__ constexpr bool fwd_streaming() {
 }
 template <typename R, int NRC, int NSC, int GEN, int EXP, int HALF>
 constexpr int fwd_waves() {
-  return !HALF ? 2 : (low_single<R, NRC, NSC, GEN, EXP>() || (sizeof(R) == 4 && NSC == 2 && NRC == 2)) ? 4 : 3;
+  return !HALF ? 2 : HALF == 2 ? 3 : (low_single<R, NRC, NSC, GEN, EXP>() || (sizeof(R) == 4 && NSC == 2 && NRC == 2)) ? 4 : 3;
 }
 template <typename R, int NRC, int NSC, int NOSTORE>
 __device__ constexpr bool bwd_streaming() {
@@ -551,7 +554,9 @@ __device__ __forceinline__ uint64_t tile_zbase(const PassDesc& D, int64_t g) {
 // compile time or -1 / 0 = read from the descriptor (the generic kernel):
 //   NRC rounds per mixer segment, NSC segments, PHM bit s = segment s starts
 //   with the cost phase, GEN synthesise |+>^n instead of loading, EXP 1 =
-//   accumulate <C> and the norm, 2 = also store lam = C psi.
+//   accumulate <C> and the norm, 2 = also store lam = C psi; HALF 0 = the
+//   tile moves through the full LDS, 1 = through half of it, 2 = as 1, at
+//   three waves per SIMD (the chunk launches of a complex64 merged pass).
 // With everything fixed the pass is straight-line code (no register merges).
 template <typename R, int LOGR, int KB, int NRC, int NSC, int PHM, int GEN, int EXP, int HALF>
 __global__ void __launch_bounds__(kMaxThreads)
@@ -560,7 +565,7 @@ __global__ void __launch_bounds__(kMaxThreads)
 k_fwd(const PassDesc* __restrict__ descs, int ndesc, LaunchMap lm) {
   constexpr int NR = 1 << LOGR;
   constexpr bool NT = NRC > 0 ? fwd_streaming<R, NRC, NSC, GEN, EXP>() : sizeof(R) == 8;
-  __shared__ cx<R> lds[1 << (KB - HALF)];
+  __shared__ cx<R> lds[1 << (KB - (HALF ? 1 : 0))];
   __shared__ double red[2 * (kMaxThreads / 64)];
   const uint32_t tid = threadIdx.x;
   const PassDesc& D = descs[ndesc > 1 ? find_desc(descs, ndesc, blockIdx.x) : 0];
@@ -1123,6 +1128,12 @@ static void launch_fwd_shaped(int shape, const PassDesc* d, int ndesc, const Lau
     QAOA_FWD_NR(1)
     QAOA_FWD_NR(2)
     QAOA_FWD_NR(3)
+    case 2 * 8 + kShapeMergedChunk:   // the planner gives it to complex64 passes only
+      if constexpr (sizeof(R) == 4)
+        launch_fwd_kernel(k_fwd<R, LOGR, KB, 2, 2, 2, 0, 0, 2>, grid, block, st, done, d, ndesc, lm);
+      else
+        launch_fwd_kernel(k_fwd<R, LOGR, KB, 2, 2, 2, 0, 0, HALF>, grid, block, st, done, d, ndesc, lm);
+      return;
     // Four rounds (the complex128 low set): a merged pass would spill.  A
     // plain single pass launched whole takes the generic full-LDS kernel (it
     // streams at copy speed there); chunked beside a high-set pass it takes
@@ -1220,16 +1231,19 @@ void pass_kernel_name(int prec, bool backward, int logr, int shape, char* buf, s
   }
   bool shaped = logr == LMAX && (((code == kShapeFirst || code == kShapeSingle || code == kShapeLast ||
                                    code == kShapeLastLam) && nrc >= 1 && nrc <= 4) ||
-                                 (code == kShapeMerged && nrc >= 1 && nrc <= 3));
+                                 (code == kShapeMerged && nrc >= 1 && nrc <= 3) ||
+                                 (code == kShapeMergedChunk && nrc == 2));
   if (!shaped) {
     snprintf(buf, len, "k_fwd<%s, %d, %d, 0, 0, -1, -1, -1, 0>", R, logr, KB);
     return;
   }
-  const int nsc = code == kShapeMerged ? 2 : 1;
-  const int phm = code == kShapeFirst ? 1 : code == kShapeMerged ? 2 : 0;
+  const bool merged = code == kShapeMerged || code == kShapeMergedChunk;
+  const int nsc = merged ? 2 : 1;
+  const int phm = code == kShapeFirst ? 1 : merged ? 2 : 0;
   const int gen = code == kShapeFirst ? 1 : 0;
   const int exp = code == kShapeLast ? 1 : code == kShapeLastLam ? 2 : 0;
-  snprintf(buf, len, "k_fwd<%s, %d, %d, %d, %d, %d, %d, %d, 1>", R, LMAX, KB, nrc, nsc, phm, gen, exp);
+  const int half = code == kShapeMergedChunk && prec == 1 ? 2 : 1;
+  snprintf(buf, len, "k_fwd<%s, %d, %d, %d, %d, %d, %d, %d, %d>", R, LMAX, KB, nrc, nsc, phm, gen, exp, half);
 }
 
 hipError_t launch_reduce(const ReduceJob* jobs, const Span* spans, int njobs, hipStream_t st) {

@@ -23,6 +23,7 @@ enum : int {
   kShapeMerged = 3,    // mixer segment, cost phase, mixer segment
   kShapeLast = 4,      // one mixer segment, then <C> and norm
   kShapeLastLam = 5,   // ... and lam = C psi
+  kShapeMergedChunk = 6,   // merged, launched per chunk as a pass pair's second pass
 };
 
 // prec: 1 = complex64, 0 = complex128.  One workgroup per tile; descriptors

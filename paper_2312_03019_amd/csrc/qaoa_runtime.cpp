@@ -340,8 +340,11 @@ static SiteDesc make_site(const SetGeom& s, int round, int logr, const HostGraph
 // maxima), whose rounds follow the half-tile pattern: [K-LOGR, K), then each
 // LOGR-1 lower, the last clamped at 0.  Anything else takes the generic kernel.
 // A four-round plain pass (the complex128 low set) is shaped only when it runs
-// chunked (`chunked`): whole, the generic full-LDS kernel is faster.
-static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const SegDesc* segs, bool chunked) {
+// chunked (`chunked`, the first pass of a pair): whole, the generic full-LDS
+// kernel is faster.  A complex64 two-round merged pass that runs chunked (the
+// second pass of a pair, `chunked2`) gets its own occupancy.
+static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const SegDesc* segs, bool chunked,
+                         bool chunked2) {
   if (d.K != pc.kmax || logr != pc.logr_max || d.nrounds < 1 || d.nrounds > 4) return 0;
   for (int i = 0; i < d.nrounds; ++i)
     if (d.rb[i] != std::max(0, d.K - logr - i * (logr - 1))) return 0;
@@ -350,7 +353,8 @@ static int forward_shape(const PassDesc& d, const PrecCfg& pc, int logr, const S
   int code = 0;
   if (d.nseg == 1 && gen && ph0 && !ex) code = kShapeFirst;
   else if (d.nseg == 1 && !gen && !ph0 && !ex && (d.nrounds <= 3 || chunked)) code = kShapeSingle;
-  else if (d.nseg == 2 && !gen && !ph0 && ph1 && !ex && d.nrounds <= 3) code = kShapeMerged;
+  else if (d.nseg == 2 && !gen && !ph0 && ph1 && !ex && d.nrounds <= 3)
+    code = chunked2 && pc.prec == 1 && d.nrounds == 2 ? kShapeMergedChunk : kShapeMerged;
   else if (d.nseg == 1 && !gen && !ph0 && ex) code = lam ? kShapeLastLam : kShapeLast;
   return code ? d.nrounds * 8 + code : 0;
 }
@@ -513,7 +517,8 @@ void build_run(const RunRequest& rq, RunImage* img) {
     if (ph_odd) fflags |= PF_SITE1;
     d.flags |= fflags;
     const bool chunked = img->chunk_bits > 0 && (i & 1) && i + 1 < sched.size();   // first pass of a pair
-    d.shape = forward_shape(d, pc, logr, img->segs.data() + seg0, chunked);
+    const bool chunked2 = img->chunk_bits > 0 && i >= 2 && !(i & 1);               // second pass of a pair
+    d.shape = forward_shape(d, pc, logr, img->segs.data() + seg0, chunked, chunked2);
     d.psi = rq.psi;
     d.lam = rq.lam;
     d.g = rq.g;
