@@ -357,3 +357,28 @@ def test_c128_low_set_kernel_by_launch_mode():
                 assert names["whole"][i] == names["chunked"][i]
     finally:
         sim.close()
+
+
+# Kernel choice for the complex64 merged pass: four waves per SIMD launched
+# whole, its own three-wave instance for the chunk launches of a pass pair;
+# every other pass keeps its kernel.
+def test_c64_merged_kernel_by_launch_mode():
+    n = 24
+    pr = _prob(391, n, "gnp", True, 0.3)
+    g, b = [0.45, 1.1, 0.8], [0.3, 1.2, 0.5]
+    sim = q.Simulator(n, pr.edges, pr.weights, "c64")
+    try:
+        names = {}
+        for label, chunk in (("whole", 0), ("chunked", 1 << 20)):
+            q.qaoa_set_chunking(sim.handle, chunk, 0, 3)
+            sim.expect(g, b)
+            names[label] = [q.qaoa_pass_kernel(sim.handle, i)[1] for i in range(2 * len(g) + 1)]
+        # sets 13 / 6 / 5 qubits: the 6-qubit set's merged pass has two rounds (pass 4),
+        # the 5-qubit set's one (pass 2, kept as it is)
+        merged = [i for i, k in enumerate(names["whole"]) if k == "k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 1>"]
+        assert merged == [4]
+        for i in range(2 * len(g) + 1):
+            want = "k_fwd<float, 5, 13, 2, 2, 2, 0, 0, 2>" if i in merged else names["whole"][i]
+            assert names["chunked"][i] == want, i
+    finally:
+        sim.close()
